@@ -1,0 +1,191 @@
+"""FP64 CPU oracle for COO MTTKRP and the sampled CP model.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+CPU-baseline leg of ``bench.py`` may import this package. The product path
+(``paper_1902_03317_amd``) never imports it, and the two share no code:
+the oracle is plain C (``mttkrp_oracle.c``, FP64, OpenMP) plus the numpy
+definitions in :mod:`oracle.brute`.
+
+What it computes (the plain definitions, Section 4.6 eq. mttkrp-init and
+Section 5.2 Alg. 6 of the suite):
+  * ``mttkrp``: out[i, r] = sum_{m: i_n(m)=i} x_m prod_{k!=n} U_k[i_k(m), r];
+  * ``cp_sample``: mhat_m = sum_r prod_k U_k[i_k(m), r];
+  * ``cp_loss``: 1/2 sum_m (mhat_m - x_m)^2 and its residuals;
+  * ``cp_grad``: d loss / d U_n = MTTKRP_n with the residuals as values;
+  * ``sort_perm`` / ``rowptr``: the stable mode-n order of the nonzeros and
+    the row offsets of the sorted stream (a library sort as the step);
+  * ``bf16_round``: float32 -> bfloat16, round to nearest, ties to even.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mttkrp_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        sig = [ctypes.c_int, P, ctypes.c_uint64, P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
+        for name in ("oracle_mttkrp_seq", "oracle_mttkrp_priv", "oracle_mttkrp_atomic"):
+            f = getattr(L, name)
+            f.argtypes = sig
+            f.restype = ctypes.c_int
+        L.oracle_cp_sample.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, ctypes.c_int, ctypes.c_int, P]
+        L.oracle_cp_sample.restype = ctypes.c_int
+        L.oracle_cp_loss.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
+        L.oracle_cp_loss.restype = ctypes.c_int
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
+
+
+class _Args:
+    """Marshal numpy arrays into the C oracle's argument layout (keeps refs alive)."""
+
+    def __init__(self, dims, inds, factors, rank=None):
+        self.N = len(dims)
+        self.dims = np.ascontiguousarray(np.asarray(dims, dtype=np.uint64))
+        inds = np.asarray(inds)
+        if inds.ndim != 2 or inds.shape[0] != self.N:
+            raise ValueError("inds must be [N, nnz]")
+        self.inds = np.ascontiguousarray(inds, dtype=np.uint32)
+        self.M = int(self.inds.shape[1])
+        self.keep = []
+        ptrs = (ctypes.c_void_p * self.N)()
+        R = None
+        ldf = None
+        for k in range(self.N):
+            f = factors[k]
+            if f is None:
+                ptrs[k] = None
+                continue
+            f = np.ascontiguousarray(np.asarray(f), dtype=np.float64)
+            if f.ndim != 2 or f.shape[0] != dims[k]:
+                raise ValueError(f"factor {k} must be [{dims[k]}, R]")
+            self.keep.append(f)
+            ptrs[k] = f.ctypes.data
+            R = f.shape[1] if R is None else R
+            ldf = f.shape[1]
+            if f.shape[1] != R:
+                raise ValueError("all factors must have R columns")
+        self.R = int(rank if rank is not None else R)
+        self.ldf = int(ldf if ldf is not None else self.R)
+        self.ptrs = ptrs
+
+
+_ERR = {-1: "bad argument", -2: "index out of range", -3: "out of memory"}
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError(f"oracle: {_ERR.get(rc, rc)}")
+
+
+def mttkrp(dims: Sequence[int], inds, vals, factors: List, mode: int, strategy: str = "seq") -> np.ndarray:
+    """Mode-``mode`` MTTKRP in FP64; ``factors[mode]`` is ignored (may be None).
+
+    strategy: "seq" (Alg. 6 generalised), "priv" (per-thread buffers, Section
+    5.3), "atomic" (atomic updates, Section 5.3) or "auto" (privatisation
+    while the private buffers fit in 16 GB, else atomics).
+    """
+    facs = [None if k == mode else factors[k] for k in range(len(dims))]
+    if all(f is None for f in facs):  # order 1: no factor, R from the caller is required
+        raise ValueError("order-1 MTTKRP needs a rank")
+    a = _Args(dims, inds, facs)
+    v = np.ascontiguousarray(np.asarray(vals), dtype=np.float64)
+    if v.shape != (a.M,):
+        raise ValueError("vals must be [nnz]")
+    out = np.empty((int(dims[mode]), a.R), dtype=np.float64)
+    if strategy == "auto":
+        strategy = "priv" if max_threads() * int(dims[mode]) * a.R * 8 <= (16 << 30) else "atomic"
+    fn = {"seq": lib().oracle_mttkrp_seq, "priv": lib().oracle_mttkrp_priv,
+          "atomic": lib().oracle_mttkrp_atomic}[strategy]
+    _check(fn(a.N, a.dims.ctypes.data, a.M, a.inds.ctypes.data, v.ctypes.data, a.ptrs, a.R, a.ldf, int(mode),
+              out.ctypes.data))
+    return out
+
+
+def cp_sample(dims, inds, factors) -> np.ndarray:
+    """mhat_m = sum_r prod_k U_k[i_k(m), r] in FP64."""
+    a = _Args(dims, inds, factors)
+    out = np.empty(a.M, dtype=np.float64)
+    _check(lib().oracle_cp_sample(a.N, a.dims.ctypes.data, a.M, a.inds.ctypes.data, a.ptrs, a.R, a.ldf,
+                                  out.ctypes.data))
+    return out
+
+
+def cp_loss(dims, inds, vals, factors):
+    """(loss, resid): resid = mhat - x, loss = 1/2 sum resid^2, FP64."""
+    a = _Args(dims, inds, factors)
+    v = np.ascontiguousarray(np.asarray(vals), dtype=np.float64)
+    resid = np.empty(a.M, dtype=np.float64)
+    loss = np.zeros(1, dtype=np.float64)
+    _check(lib().oracle_cp_loss(a.N, a.dims.ctypes.data, a.M, a.inds.ctypes.data, v.ctypes.data, a.ptrs, a.R,
+                                a.ldf, resid.ctypes.data, loss.ctypes.data))
+    return float(loss[0]), resid
+
+
+def cp_grad(dims, inds, vals, factors, strategy: str = "seq"):
+    """(loss, [dL/dU_n]) of the observed-entry least-squares CP loss, FP64."""
+    loss, resid = cp_loss(dims, inds, vals, factors)
+    grads = [mttkrp(dims, inds, resid, factors, n, strategy) for n in range(len(dims))]
+    return loss, grads
+
+
+def sort_perm(rows) -> np.ndarray:
+    """Stable order of the nonzeros by their mode-n index (ties keep caller order)."""
+    return np.argsort(np.asarray(rows), kind="stable").astype(np.uint32)
+
+
+def rowptr(sorted_rows, size: int) -> np.ndarray:
+    """rowptr[i] = first position of row i in the sorted stream; rowptr[size] = nnz."""
+    return np.searchsorted(np.asarray(sorted_rows), np.arange(size + 1), side="left").astype(np.uint32)
+
+
+def bf16_round(a) -> np.ndarray:
+    """float32 -> bfloat16 by round-to-nearest-even on the bit pattern, as float32 values."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32)
+
+
+def bf16_bits(a) -> np.ndarray:
+    """The uint16 bit patterns of ``bf16_round(a)``."""
+    return (bf16_round(a).view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+
+
+def rel_fro(y, ystar) -> float:
+    """||y - y*||_F / ||y*||_F; if ||y*|| = 0 the result is ||y|| (must be exactly 0)."""
+    y = np.asarray(y, dtype=np.float64)
+    ystar = np.asarray(ystar, dtype=np.float64)
+    den = float(np.linalg.norm(ystar))
+    num = float(np.linalg.norm(y - ystar))
+    return num / den if den > 0 else float(np.linalg.norm(y))

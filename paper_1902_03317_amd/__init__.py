@@ -1,0 +1,23 @@
+"""MI355X-native COO MTTKRP (mode-n matricized tensor times Khatri-Rao product).
+
+The compute path lives in ``libpasta.so`` (HIP kernels for gfx950 behind a
+C ABI, declared in ``include/pasta.h``); this package is its thin Python
+binding. The binding is loaded on first use of the API, so the input
+generator in :mod:`.synth` can be imported without it.
+"""
+
+__all__ = ["Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16",
+           "CPSample", "CPLoss", "lib"]
+
+
+def __getattr__(name):
+    if name in ("Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16"):
+        from . import api
+        return getattr(api, name)
+    if name in ("CPSample", "CPLoss"):
+        from . import autograd
+        return getattr(autograd, name)
+    if name == "lib":
+        from . import _lib
+        return _lib
+    raise AttributeError(name)
