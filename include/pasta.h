@@ -1,0 +1,188 @@
+/*
+ * pasta.h - C ABI of the MI355X (gfx950) COO MTTKRP library (libpasta.so).
+ *
+ * The operation is the mode-n MTTKRP of a sparse tensor stored in COO form
+ * (Section 4.6, eq. mttkrp-init; Section 5.2, Alg. 6 and its text):
+ *
+ *     out[i][r] = alpha * sum over nonzeros m with i_n(m) = i of
+ *                 x(m) * prod_{k != n} U^(k)[i_k(m)][r],
+ *
+ * for every row i of mode n (rows without nonzeros are zero), plus the
+ * sampled CP model and its residual-weighted MTTKRP gradient (CP
+ * decomposition, Section 3.1.1).
+ *
+ * Conventions shared by every entry point
+ *   - Coordinates are 0-based (the COO example of Section 5.1); indices are
+ *     uint32 and values fp32 (the storage assumption of Table 2).
+ *   - Factor U^(k) is row-major I_k x ldf, element type fp32 or bf16, only
+ *     the first R columns are read (Alg. 6 addresses rows as i*R + r).
+ *   - Outputs are fp32, row-major with leading dimension ldo; only columns
+ *     0..R-1 are written.
+ *   - Every pointer named d_* is HIP device memory owned by the caller; the
+ *     library allocates no device memory. Host arrays are read during the
+ *     call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     All work is enqueued on it and the call returns without waiting,
+ *     except pasta_coo_create, which waits once for its index check.
+ *   - Argument errors are reported synchronously through the return value
+ *     and nothing is enqueued; the library never aborts or throws.
+ *   - Calls that share a handle may run concurrently only if they do not
+ *     share a workspace or an output buffer.
+ */
+#ifndef PASTA_H
+#define PASTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PASTA_OK = 0,
+    PASTA_EINVAL = 1,       /* a null pointer, a zero size, mode >= order, ld < rank, ... */
+    PASTA_ERANGE = 2,       /* some coordinate is >= its dimension */
+    PASTA_EUNSUPPORTED = 3, /* order, rank, dtype or alignment outside the supported set */
+    PASTA_EWORKSPACE = 4,   /* workspace smaller than the queried size, or not 256-byte aligned */
+    PASTA_EHIP = 5          /* a HIP runtime call failed; see pasta_last_hip_error() */
+} pasta_status;
+
+typedef enum { PASTA_F32 = 0, PASTA_BF16 = 1 } pasta_dtype;
+
+/* Opaque host-side handle of a preprocessed COO tensor. It points into the
+ * caller's workspace and the caller's original index/value arrays, which
+ * must stay alive and unchanged until pasta_coo_destroy. */
+typedef struct pasta_coo pasta_coo;
+
+/* Supported ranges. */
+#define PASTA_MAX_ORDER 8
+#define PASTA_MAX_RANK 256
+
+/* Bytes of device workspace that pasta_coo_create needs for an order-N
+ * tensor with these dimensions and nnz nonzeros (nnz < 2^32, 2 <= N <= 8,
+ * 1 <= dims[k] <= 2^31). Holds, for every mode, the nonzeros sorted by
+ * that mode's index (SoA), the sort permutation and the row offsets. */
+pasta_status pasta_coo_workspace_bytes(uint32_t order, const uint64_t *dims, uint64_t nnz, size_t *bytes);
+
+/* Preprocess a COO tensor (the sorting and fiber/row pointers the suite
+ * builds before its kernels, Section 5.2): checks every coordinate against
+ * its dimension, then for every mode n stably sorts the nonzeros by i_n
+ * (ties keep the caller's order), stores the sorted copy, the permutation
+ * and the row offsets in the workspace.
+ *   d_inds  host array of `order` device pointers; d_inds[k][m] = i_k(m).
+ *   d_vals  device array of nnz fp32 values.
+ *   d_workspace  >= pasta_coo_workspace_bytes, 256-byte aligned.
+ * Waits for the stream once. Returns PASTA_ERANGE (and no handle) if any
+ * coordinate is out of range. On success *out owns only host memory. */
+pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz, const uint32_t *const *d_inds,
+                              const float *d_vals, void *d_workspace, size_t workspace_bytes, void *stream,
+                              pasta_coo **out);
+
+/* Free the host handle. Device memory stays the caller's. */
+pasta_status pasta_coo_destroy(pasta_coo *X);
+
+/* Order and nonzero count of a handle. */
+pasta_status pasta_coo_info(const pasta_coo *X, uint32_t *order, uint64_t *nnz);
+
+/* Device views of the mode-`mode` preprocessing (all read-only, valid
+ * while the workspace lives). Any output pointer may be NULL.
+ *   d_perm[p]    caller position of the p-th nonzero in mode order (nnz);
+ *   d_rowptr[i]  first position of row i in mode order (dims[mode] + 1);
+ *   d_sorted_inds  host array of `order` pointers, filled with the sorted
+ *                  index arrays (nnz each);
+ *   d_sorted_vals  the values in mode order (nnz). */
+pasta_status pasta_coo_mode_view(const pasta_coo *X, uint32_t mode, const uint32_t **d_perm,
+                                 const uint32_t **d_rowptr, const uint32_t **d_sorted_inds,
+                                 const float **d_sorted_vals);
+
+/* Bytes of scratch workspace pasta_mttkrp needs for this mode and rank
+ * (partial rows of the chunks a row spans). */
+pasta_status pasta_mttkrp_workspace_bytes(const pasta_coo *X, uint32_t mode, uint32_t rank, pasta_dtype dtype,
+                                          size_t *bytes);
+
+/* Mode-n MTTKRP (eq. mttkrp-init; Alg. 6 for order N and any mode):
+ *   d_factors  host array of `order` device pointers; d_factors[mode] is
+ *              not read and may be NULL.
+ *   dtype      element type of every factor (fp32 or bf16; arithmetic and
+ *              accumulation are fp32 either way).
+ *   rank R     1..PASTA_MAX_RANK; ldf >= R (elements).
+ *   d_vals_override  NULL to use the tensor's values, else nnz fp32 values
+ *              in the caller's order used instead (the residual-weighted
+ *              MTTKRP of a CP gradient).
+ *   alpha      scale applied to the result.
+ *   d_out      dims[mode] x ldo fp32, OVERWRITTEN (every row, empty rows
+ *              get zeros); ldo >= R.
+ *   d_work     >= pasta_mttkrp_workspace_bytes, 256-byte aligned.
+ * The result is deterministic: the same inputs give the same bits. */
+pasta_status pasta_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                          uint32_t rank, uint32_t ldf, const float *d_vals_override, float alpha, float *d_out,
+                          uint32_t ldo, void *d_work, size_t work_bytes, void *stream);
+
+/* The same product computed the way the suite's parallel CPU code does with
+ * atomics (Section 5.3): nonzeros in caller order, one atomic row update
+ * per nonzero, no sorting. Kept as a reference point for measurements;
+ * not deterministic in the last bits. d_out is overwritten. */
+pasta_status pasta_mttkrp_atomic(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                                 uint32_t rank, uint32_t ldf, float *d_out, uint32_t ldo, void *stream);
+
+/* Rank-R CP model sampled at the nonzeros (CP decomposition, Section
+ * 3.1.1): d_mhat[m] = sum_r prod_k U^(k)[i_k(m)][r], in caller order.
+ * Every factor is read, including all modes. */
+pasta_status pasta_cp_sample(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype, uint32_t rank,
+                             uint32_t ldf, float *d_mhat, void *stream);
+
+/* Bytes of scratch for pasta_cp_residual_loss (fp64 loss partials). */
+pasta_status pasta_cp_workspace_bytes(const pasta_coo *X, uint32_t rank, pasta_dtype dtype, size_t *bytes);
+
+/* Residual and loss of the observed-entry least-squares CP fit:
+ *   d_resid[m] = mhat(m) - x(m) (caller order, fp32; may be NULL),
+ *   *d_loss    = 1/2 sum_m resid(m)^2, accumulated in fp64 (device scalar).
+ * d_work >= pasta_cp_workspace_bytes. */
+pasta_status pasta_cp_residual_loss(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype,
+                                    uint32_t rank, uint32_t ldf, float *d_resid, double *d_loss, void *d_work,
+                                    size_t work_bytes, void *stream);
+
+/* Loss and gradient of the observed-entry least-squares CP fit in one pass
+ * per mode: for every mode n,
+ *   d_grads[n] = alpha * dL/dU^(n) = alpha * MTTKRP_n(values = mhat - x),
+ * with the residual recomputed in mode-n order (never stored), and
+ *   *d_loss = 1/2 sum_m (mhat(m) - x(m))^2 in fp64 (may be NULL).
+ * d_grads: host array of `order` device pointers, each dims[n] x ldg fp32,
+ * overwritten. d_work >= max over modes of pasta_mttkrp_workspace_bytes
+ * plus pasta_cp_workspace_bytes (see pasta_cp_grad_workspace_bytes). */
+pasta_status pasta_cp_grad_workspace_bytes(const pasta_coo *X, uint32_t rank, pasta_dtype dtype, size_t *bytes);
+pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype, uint32_t rank,
+                           uint32_t ldf, float alpha, float *const *d_grads, uint32_t ldg, double *d_loss,
+                           void *d_work, size_t work_bytes, void *stream);
+
+/* fp32 -> bf16 with round to nearest, ties to even (NaN stays NaN):
+ * d_dst[i] = bf16(d_src[i]) for i < count, bf16 given as uint16 bits. */
+pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_t count, void *stream);
+
+/* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
+ * derivative held on the device (no host round trip). */
+pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream);
+
+/* One Adam step on fp32 parameters (the optimiser of a gradient-based CP fit,
+ * a gradient-descent CPD method as listed in Section 3.1.1), in place:
+ *   m = b1*m + (1-b1)*g;  v = b2*v + (1-b2)*g^2;
+ *   p -= lr/(1-b1^t) * m / (sqrt(v)/sqrt(1-b2^t) + eps),  t = step >= 1;
+ * if d_shadow_bf16 is not NULL the updated p is also written there as bf16
+ * (round to nearest even), which is the factor copy a bf16 step reads.
+ * All arrays hold `count` elements. */
+pasta_status pasta_adam_step(float *d_param, const float *d_grad, float *d_m, float *d_v, uint16_t *d_shadow_bf16,
+                             uint64_t count, float lr, float beta1, float beta2, float eps, uint32_t step,
+                             void *stream);
+
+/* Text of a status code (static storage). */
+const char *pasta_status_str(pasta_status s);
+
+/* The hipError_t of the last HIP failure on the calling thread (0 if none). */
+int pasta_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PASTA_H */

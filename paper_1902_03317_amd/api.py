@@ -1,0 +1,219 @@
+"""Python API over libpasta. torch supplies device memory and streams; every
+computation is a call into the HIP library through the C ABI."""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, lib, ptr_array
+
+_DT = {torch.float32: _lib.PASTA_F32, torch.bfloat16: _lib.PASTA_BF16}
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _scratch(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Coo:
+    """A COO tensor preprocessed for MTTKRP on one GPU.
+
+    ``inds`` is an int32/uint32-valued tensor [N, nnz] (or N tensors [nnz])
+    of 0-based coordinates and ``vals`` float32 [nnz], both on the GPU. For
+    every mode the library keeps a copy of the nonzeros sorted stably by that
+    mode's index, in a workspace this object owns.
+    """
+
+    def __init__(self, dims: Sequence[int], inds, vals: torch.Tensor, stream=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.order = len(self.dims)
+        rows = list(inds) if not isinstance(inds, torch.Tensor) else [inds[k] for k in range(inds.shape[0])]
+        if len(rows) != self.order:
+            raise ValueError(f"need {self.order} index arrays, got {len(rows)}")
+        self.inds = [r.contiguous() for r in rows]
+        for r in self.inds:
+            if r.dtype != torch.int32 or not r.is_cuda:
+                raise TypeError("indices must be int32 CUDA tensors (uint32 bit patterns)")
+        self.vals = vals.contiguous()
+        if self.vals.dtype != torch.float32 or not self.vals.is_cuda:
+            raise TypeError("values must be a float32 CUDA tensor")
+        self.nnz = int(self.vals.numel())
+        if any(int(r.numel()) != self.nnz for r in self.inds):
+            raise ValueError("index arrays and values differ in length")
+        self.device = self.vals.device
+        self._dims_c = (ctypes.c_uint64 * self.order)(*self.dims)
+        nbytes = ctypes.c_size_t()
+        check(lib.pasta_coo_workspace_bytes(self.order, self._dims_c, self.nnz, ctypes.byref(nbytes)),
+              "pasta_coo_workspace_bytes")
+        self.workspace = _scratch(nbytes.value, self.device)
+        self._ind_ptrs = ptr_array([r.data_ptr() for r in self.inds])
+        h = ctypes.c_void_p()
+        check(lib.pasta_coo_create(self.order, self._dims_c, self.nnz, self._ind_ptrs, self.vals.data_ptr(),
+                                   self.workspace.data_ptr(), self.workspace.numel(), _stream(stream),
+                                   ctypes.byref(h)), "pasta_coo_create")
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.pasta_coo_destroy(h)
+            self._h = None
+
+    def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
+        off = ptr - self.workspace.data_ptr()
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.workspace[off: off + count * esz].view(dtype)
+
+    def mode_view(self, mode: int):
+        """(perm, rowptr, sorted index arrays [N], sorted values) of one mode, as views."""
+        perm, rowptr, vals = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        sinds = (ctypes.c_void_p * self.order)()
+        check(lib.pasta_coo_mode_view(self._h, int(mode), ctypes.byref(perm), ctypes.byref(rowptr), sinds,
+                                      ctypes.byref(vals)), "pasta_coo_mode_view")
+        M = self.nnz
+        return (self._view(perm.value, M, torch.int32), self._view(rowptr.value, self.dims[mode] + 1, torch.int32),
+                [self._view(sinds[k], M, torch.int32) for k in range(self.order)],
+                self._view(vals.value, M, torch.float32))
+
+
+def _factor_args(X: Coo, factors: Sequence[Optional[torch.Tensor]], skip: Optional[int]):
+    ref = None
+    for k, f in enumerate(factors):
+        if f is None:
+            if k != skip:
+                raise ValueError(f"factor {k} is required")
+            continue
+        if not f.is_cuda or f.dim() != 2 or f.stride(1) != 1:
+            raise ValueError(f"factor {k} must be a 2-D CUDA tensor with unit column stride")
+        if f.shape[0] != X.dims[k]:
+            raise ValueError(f"factor {k} has {f.shape[0]} rows, mode size is {X.dims[k]}")
+        if ref is None:
+            ref = f
+        elif f.dtype != ref.dtype or f.shape[1] != ref.shape[1] or f.stride(0) != ref.stride(0):
+            raise ValueError("all factors need the same dtype, rank and row stride")
+    if ref is None:
+        raise ValueError("no factor given")
+    if ref.dtype not in _DT:
+        raise TypeError("factors must be float32 or bfloat16")
+    ptrs = ptr_array([0 if f is None else f.data_ptr() for f in factors])
+    return ptrs, _DT[ref.dtype], int(ref.shape[1]), int(max(ref.stride(0), ref.shape[1]))
+
+
+def mttkrp_workspace_bytes(X: Coo, mode: int, rank: int, dtype=torch.float32) -> int:
+    n = ctypes.c_size_t()
+    check(lib.pasta_mttkrp_workspace_bytes(X.handle, int(mode), int(rank), _DT[dtype], ctypes.byref(n)),
+          "pasta_mttkrp_workspace_bytes")
+    return n.value
+
+
+def mttkrp(X: Coo, factors: Sequence[Optional[torch.Tensor]], mode: int, out: Optional[torch.Tensor] = None,
+           vals: Optional[torch.Tensor] = None, alpha: float = 1.0, workspace: Optional[torch.Tensor] = None,
+           stream=None) -> torch.Tensor:
+    """out = alpha * MTTKRP_mode(X; factors), fp32 [dims[mode], R]; factors[mode] is not read.
+
+    ``vals`` (float32 [nnz], caller order) replaces the tensor's values."""
+    facs = list(factors)
+    if not (0 <= mode < X.order):
+        raise ValueError("mode out of range")
+    facs[mode] = None if facs[mode] is None else facs[mode]
+    ptrs, dt, R, ldf = _factor_args(X, [None if k == mode else f for k, f in enumerate(facs)], mode)
+    if out is None:
+        out = torch.empty((X.dims[mode], R), dtype=torch.float32, device=X.device)
+    if out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != X.dims[mode] or out.shape[1] < R \
+            or out.stride(1) != 1:
+        raise ValueError("out must be float32 [dims[mode], >=R] with unit column stride")
+    vptr = None
+    if vals is not None:
+        if vals.dtype != torch.float32 or vals.numel() != X.nnz or not vals.is_contiguous():
+            raise ValueError("vals must be a contiguous float32 tensor of nnz entries")
+        vptr = vals.data_ptr()
+    if workspace is None:
+        workspace = _scratch(mttkrp_workspace_bytes(X, mode, R, facs[(mode + 1) % X.order].dtype), X.device)
+    check(lib.pasta_mttkrp(X.handle, int(mode), ptrs, dt, R, ldf, vptr, float(alpha), out.data_ptr(),
+                           int(out.stride(0)), workspace.data_ptr(), workspace.numel(), _stream(stream)),
+          "pasta_mttkrp")
+    return out
+
+
+def mttkrp_atomic(X: Coo, factors, mode: int, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The nonzero-parallel atomic-update form of MTTKRP (for comparison)."""
+    ptrs, dt, R, ldf = _factor_args(X, [None if k == mode else f for k, f in enumerate(factors)], mode)
+    if out is None:
+        out = torch.empty((X.dims[mode], R), dtype=torch.float32, device=X.device)
+    check(lib.pasta_mttkrp_atomic(X.handle, int(mode), ptrs, dt, R, ldf, out.data_ptr(), int(out.stride(0)),
+                                  _stream(stream)), "pasta_mttkrp_atomic")
+    return out
+
+
+def cp_sample(X: Coo, factors, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """mhat[m] = sum_r prod_k U_k[i_k(m), r] at every nonzero, caller order, fp32."""
+    ptrs, dt, R, ldf = _factor_args(X, factors, None)
+    if out is None:
+        out = torch.empty(X.nnz, dtype=torch.float32, device=X.device)
+    check(lib.pasta_cp_sample(X.handle, ptrs, dt, R, ldf, out.data_ptr(), _stream(stream)), "pasta_cp_sample")
+    return out
+
+
+def cp_residual_loss(X: Coo, factors, resid: Optional[torch.Tensor] = None, want_resid: bool = True,
+                     stream=None):
+    """(resid = mhat - x [fp32, caller order] or None, loss = 1/2 sum resid^2 [fp64 scalar tensor])."""
+    ptrs, dt, R, ldf = _factor_args(X, factors, None)
+    if resid is None and want_resid:
+        resid = torch.empty(X.nnz, dtype=torch.float32, device=X.device)
+    loss = torch.empty((), dtype=torch.float64, device=X.device)
+    n = ctypes.c_size_t()
+    check(lib.pasta_cp_workspace_bytes(X.handle, R, dt, ctypes.byref(n)), "pasta_cp_workspace_bytes")
+    ws = _scratch(n.value, X.device)
+    check(lib.pasta_cp_residual_loss(X.handle, ptrs, dt, R, ldf, None if resid is None else resid.data_ptr(),
+                                     loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
+          "pasta_cp_residual_loss")
+    return resid, loss
+
+
+def cp_grad_workspace_bytes(X: Coo, rank: int, dtype=torch.float32) -> int:
+    n = ctypes.c_size_t()
+    check(lib.pasta_cp_grad_workspace_bytes(X.handle, int(rank), _DT[dtype], ctypes.byref(n)),
+          "pasta_cp_grad_workspace_bytes")
+    return n.value
+
+
+def cp_grad(X: Coo, factors, grads: Optional[List[torch.Tensor]] = None, alpha: float = 1.0,
+            want_loss: bool = True, workspace: Optional[torch.Tensor] = None, stream=None):
+    """(loss [fp64 scalar tensor or None], [alpha * dL/dU_n]) for L = 1/2 sum_m (mhat_m - x_m)^2."""
+    ptrs, dt, R, ldf = _factor_args(X, factors, None)
+    if grads is None:
+        grads = [torch.empty((d, R), dtype=torch.float32, device=X.device) for d in X.dims]
+    ldg = int(grads[0].stride(0))
+    for n, g in enumerate(grads):
+        if g.dtype != torch.float32 or g.shape[0] != X.dims[n] or g.shape[1] < R or g.stride(1) != 1 \
+                or int(g.stride(0)) != ldg:
+            raise ValueError("grads must be float32 [dims[n], >=R] sharing one row stride")
+    loss = torch.empty((), dtype=torch.float64, device=X.device) if want_loss else None
+    if workspace is None:
+        workspace = _scratch(cp_grad_workspace_bytes(X, R, factors[0].dtype), X.device)
+    check(lib.pasta_cp_grad(X.handle, ptrs, dt, R, ldf, float(alpha), ptr_array([g.data_ptr() for g in grads]),
+                            ldg, None if loss is None else loss.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                            _stream(stream)), "pasta_cp_grad")
+    return loss, grads
+
+
+def cast_bf16(src: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """fp32 -> bf16 (round to nearest even) with the library's cast kernel."""
+    if src.dtype != torch.float32 or not src.is_contiguous():
+        raise ValueError("src must be contiguous float32")
+    if out is None:
+        out = torch.empty(src.shape, dtype=torch.bfloat16, device=src.device)
+    check(lib.pasta_cast_f32_to_bf16(src.data_ptr(), out.data_ptr(), src.numel(), _stream(stream)),
+          "pasta_cast_f32_to_bf16")
+    return out

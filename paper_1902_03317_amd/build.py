@@ -1,0 +1,72 @@
+"""Compile libpasta.so (HIP, gfx950) in-tree.
+
+    python -m paper_1902_03317_amd.build
+
+Every source is compiled with hipcc for gfx950 only; the per-order kernel
+file is compiled once per tensor order (PASTA_NM1 = order - 1).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libpasta.so")
+ARCH = "gfx950"
+ORDERS = range(2, 9)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+    # packed fp32 arithmetic stays off: only scalar fp32 VALU ops are emitted
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-parameter",
+]
+
+
+def _jobs():
+    srcs = [(os.path.join(CSRC, "api.hip"), "api.o", []),
+            (os.path.join(CSRC, "preprocess.hip"), "preprocess.o", [])]
+    for n in ORDERS:
+        srcs.append((os.path.join(CSRC, "kernels_order.hip"), f"kernels_order{n}.o", [f"-DPASTA_NM1={n - 1}"]))
+    return srcs
+
+
+def _compile(job):
+    src, obj, extra = job
+    out = os.path.join(OBJ, obj)
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {obj}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return out
+
+
+def build(jobs: int = 8, verbose: bool = False) -> str:
+    """Compile every HIP source and link libpasta.so; returns its path."""
+    os.makedirs(OBJ, exist_ok=True)
+    with ThreadPoolExecutor(max(1, jobs)) as ex:
+        objs = list(ex.map(_compile, _jobs()))
+    tmp = LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return LIB
+
+
+def clean():
+    shutil.rmtree(OBJ, ignore_errors=True)
+
+
+if __name__ == "__main__":
+    build(jobs=int(os.environ.get("MAX_JOBS", "8")), verbose=True)
+    sys.exit(0)

@@ -1,0 +1,635 @@
+// Host side of libpasta: argument checks, workspace layout, kernel choice
+// and stream ordering behind the C ABI declared in include/pasta.h.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/pasta.h"
+#include "common.h"
+
+using namespace pasta;
+
+struct pasta_coo {
+    uint32_t order;
+    uint64_t nnz;
+    uint64_t dims[kMaxOrder];
+    const uint32_t *inds[kMaxOrder];  // caller order (caller-owned)
+    const float *vals;
+    struct Mode {
+        uint32_t *sinds[kMaxOrder];  // sorted copies; sinds[n] holds i_n itself
+        float *svals;
+        uint32_t *perm;
+        uint32_t *rowptr;
+    } mode[kMaxOrder];
+};
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+#define HIPCHK(expr)                                                                                             \
+    do {                                                                                                         \
+        hipError_t e_ = (expr);                                                                                  \
+        if (e_ != hipSuccess) {                                                                                  \
+            g_last_hip_error = (int)e_;                                                                          \
+            return PASTA_EHIP;                                                                                   \
+        }                                                                                                        \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr uint32_t kSub = 256;            // nonzeros per lane group per chunk
+constexpr uint32_t kSampleTilesPerWave = 16;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct CooLayout {
+    size_t sinds[kMaxOrder][kMaxOrder];
+    size_t svals[kMaxOrder], perm[kMaxOrder], rowptr[kMaxOrder];
+    size_t flag, keysA, permA, keysB, permB, hist, scanpart;
+    size_t total;
+    uint32_t ntiles;
+};
+
+bool checked_add(size_t &off, size_t bytes)
+{
+    const size_t a = align_up(bytes);
+    if (off > SIZE_MAX - a) return false;
+    off += a;
+    return true;
+}
+
+bool make_layout(uint32_t N, const uint64_t *dims, uint64_t nnz, CooLayout &L)
+{
+    size_t off = 0;
+    const size_t m4 = (size_t)nnz * 4;
+    for (uint32_t n = 0; n < N; ++n) {
+        for (uint32_t k = 0; k < N; ++k) {
+            L.sinds[n][k] = off;
+            if (!checked_add(off, m4)) return false;
+        }
+        L.svals[n] = off;
+        if (!checked_add(off, m4)) return false;
+        L.perm[n] = off;
+        if (!checked_add(off, m4)) return false;
+        L.rowptr[n] = off;
+        if (!checked_add(off, ((size_t)dims[n] + 1) * 4)) return false;
+    }
+    L.flag = off;
+    checked_add(off, 4);
+    L.keysA = off;
+    checked_add(off, m4);
+    L.permA = off;
+    checked_add(off, m4);
+    L.keysB = off;
+    checked_add(off, m4);
+    L.permB = off;
+    checked_add(off, m4);
+    L.ntiles = (uint32_t)std::max<uint64_t>(1, (nnz + kSortTile - 1) / kSortTile);
+    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    L.hist = off;
+    checked_add(off, hist_n * 4);
+    L.scanpart = off;
+    if (!checked_add(off, scan_partials_count(hist_n) * 4 + 4)) return false;
+    L.total = off;
+    return true;
+}
+
+pasta_status check_shape(uint32_t N, const uint64_t *dims, uint64_t nnz)
+{
+    if (!dims) return PASTA_EINVAL;
+    if (N < 2 || N > (uint32_t)kMaxOrder) return PASTA_EUNSUPPORTED;
+    if (nnz >= (1ull << 32)) return PASTA_EUNSUPPORTED;
+    for (uint32_t k = 0; k < N; ++k) {
+        if (dims[k] == 0) return PASTA_EINVAL;
+        if (dims[k] > (1ull << 31)) return PASTA_EUNSUPPORTED;
+    }
+    return PASTA_OK;
+}
+
+int key_bits(uint64_t dim)
+{
+    int b = 0;
+    while (b < 32 && (1ull << b) < dim) ++b;
+    return b;  // indices are < dim <= 2^b
+}
+
+uint32_t next_pow2(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Kernel shape for a rank / dtype / leading-dimension combination.
+bool choose_shape(pasta_dtype dt, uint32_t R, uint32_t ldf, uint32_t ldo, const void *const *facs, uint32_t nf,
+                  const void *out, KernelShape &s)
+{
+    bool al = out == nullptr || aligned16(out);
+    for (uint32_t k = 0; k < nf; ++k) al = al && (facs[k] == nullptr || aligned16(facs[k]));
+    const uint32_t vec = dt == PASTA_F32 ? 4 : 8;
+    if (al && R % vec == 0 && ldf % vec == 0 && ldo % 4 == 0 && R / vec <= 16) {
+        s.vec = (int)vec;
+        s.lanes = (int)next_pow2(R / vec);
+        s.strided = false;
+        return true;
+    }
+    if (R <= 256) {
+        s.vec = 4;
+        s.lanes = 64;
+        s.strided = true;
+        return true;
+    }
+    return false;
+}
+
+hipError_t launch_mttkrp(uint32_t N, const MttkrpLaunch &l, bool bf16, KernelShape s, bool fused, hipStream_t st)
+{
+    switch (N - 1) {
+    case 1: return launch_mttkrp_nm1_1(l, bf16, s, fused, st);
+    case 2: return launch_mttkrp_nm1_2(l, bf16, s, fused, st);
+    case 3: return launch_mttkrp_nm1_3(l, bf16, s, fused, st);
+    case 4: return launch_mttkrp_nm1_4(l, bf16, s, fused, st);
+    case 5: return launch_mttkrp_nm1_5(l, bf16, s, fused, st);
+    case 6: return launch_mttkrp_nm1_6(l, bf16, s, fused, st);
+    case 7: return launch_mttkrp_nm1_7(l, bf16, s, fused, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sample(uint32_t N, const SampleLaunch &l, bool bf16, KernelShape s, hipStream_t st)
+{
+    switch (N - 1) {
+    case 1: return launch_sample_nm1_1(l, bf16, s, st);
+    case 2: return launch_sample_nm1_2(l, bf16, s, st);
+    case 3: return launch_sample_nm1_3(l, bf16, s, st);
+    case 4: return launch_sample_nm1_4(l, bf16, s, st);
+    case 5: return launch_sample_nm1_5(l, bf16, s, st);
+    case 6: return launch_sample_nm1_6(l, bf16, s, st);
+    case 7: return launch_sample_nm1_7(l, bf16, s, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_atomic(uint32_t N, const AtomicLaunch &l, bool bf16, KernelShape s, hipStream_t st)
+{
+    switch (N - 1) {
+    case 1: return launch_atomic_nm1_1(l, bf16, s, st);
+    case 2: return launch_atomic_nm1_2(l, bf16, s, st);
+    case 3: return launch_atomic_nm1_3(l, bf16, s, st);
+    case 4: return launch_atomic_nm1_4(l, bf16, s, st);
+    case 5: return launch_atomic_nm1_5(l, bf16, s, st);
+    case 6: return launch_atomic_nm1_6(l, bf16, s, st);
+    case 7: return launch_atomic_nm1_7(l, bf16, s, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Geometry of one MTTKRP call: chunking of the mode-ordered stream and the
+// partial-row scratch it needs.
+struct MttkrpPlan {
+    KernelShape shape;
+    uint32_t sub, nchunks, ldp;
+    uint64_t chunk;
+    size_t part_bytes;
+};
+
+bool plan_mttkrp(const pasta_coo *X, uint32_t rank, KernelShape s, MttkrpPlan &p)
+{
+    p.shape = s;
+    const uint32_t G = 64u / (uint32_t)s.lanes;
+    p.sub = kSub;
+    p.chunk = (uint64_t)p.sub * G;
+    const uint64_t nch = (X->nnz + p.chunk - 1) / p.chunk;
+    if (nch > 0x7FFFFFFFull) return false;
+    p.nchunks = (uint32_t)nch;
+    p.ldp = s.strided ? rank : (rank + 3u) / 4u * 4u;
+    p.part_bytes = align_up((size_t)2 * p.nchunks * p.ldp * sizeof(float));
+    return true;
+}
+
+// Worst case over kernel shapes for a rank: the contiguous shape has the most chunks.
+size_t mttkrp_ws_bound(const pasta_coo *X, uint32_t rank, pasta_dtype dt)
+{
+    size_t best = 0;
+    KernelShape shapes[2];
+    const uint32_t vec = dt == PASTA_F32 ? 4 : 8;
+    shapes[0] = {(int)vec, (int)next_pow2(std::max<uint32_t>(1, (rank + vec - 1) / vec)), false};
+    shapes[1] = {4, 64, true};
+    for (auto &s : shapes) {
+        if (s.lanes > 16 && !s.strided) continue;
+        MttkrpPlan p;
+        if (plan_mttkrp(X, rank, s, p)) best = std::max(best, p.part_bytes);
+    }
+    return best;
+}
+
+size_t sample_blocks(uint64_t nnz)
+{
+    const uint64_t tiles = (nnz + 63) / 64;
+    const uint64_t waves = (tiles + kSampleTilesPerWave - 1) / kSampleTilesPerWave;
+    return (size_t)std::max<uint64_t>(1, (waves + 3) / 4);
+}
+
+pasta_status check_factors(const pasta_coo *X, const void *const *facs, uint32_t skip_mode)
+{
+    if (!facs) return PASTA_EINVAL;
+    for (uint32_t k = 0; k < X->order; ++k)
+        if (k != skip_mode && facs[k] == nullptr) return PASTA_EINVAL;
+    return PASTA_OK;
+}
+
+pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *facs, pasta_dtype dt, uint32_t rank,
+                        uint32_t ldf, const float *ovr, float alpha, float *out, uint32_t ldo, void *work,
+                        size_t work_bytes, bool fused, double *loss_part, hipStream_t st)
+{
+    const void *fl[kMaxOrder];
+    uint32_t nf = 0;
+    for (uint32_t k = 0; k < X->order; ++k)
+        if (k != mode || fused) fl[nf++] = facs[k];
+    KernelShape s;
+    if (!choose_shape(dt, rank, ldf, ldo, fl, nf, out, s)) return PASTA_EUNSUPPORTED;
+    MttkrpPlan p;
+    if (!plan_mttkrp(X, rank, s, p)) return PASTA_EUNSUPPORTED;
+    if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
+        return PASTA_EWORKSPACE;
+    const auto &md = X->mode[mode];
+    MttkrpLaunch l{};
+    l.row = md.sinds[mode];
+    uint32_t q = 0;
+    for (uint32_t k = 0; k < X->order; ++k) {
+        if (k == mode) continue;
+        l.idx[q] = md.sinds[k];
+        l.fac[q] = facs[k];
+        ++q;
+    }
+    l.facn = fused ? facs[mode] : nullptr;
+    l.vals = ovr ? ovr : md.svals;
+    l.perm = ovr ? md.perm : nullptr;
+    l.out = out;
+    l.part = static_cast<float *>(work);
+    l.loss_part = loss_part;
+    l.nnz = X->nnz;
+    l.ldf = ldf;
+    l.ldo = ldo;
+    l.ldp = p.ldp;
+    l.rank = rank;
+    l.sub = p.sub;
+    l.nchunks = p.nchunks;
+    l.alpha = alpha;
+    if (X->nnz > 0) HIPCHK(launch_mttkrp(X->order, l, dt == PASTA_BF16, s, fused, st));
+    HIPCHK(launch_fixup(md.rowptr, (uint32_t)X->dims[mode], l.part, p.ldp, out, ldo, rank, p.chunk, alpha, s, st));
+    return PASTA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pasta_status pasta_coo_workspace_bytes(uint32_t order, const uint64_t *dims, uint64_t nnz, size_t *bytes)
+{
+    if (!bytes) return PASTA_EINVAL;
+    pasta_status s = check_shape(order, dims, nnz);
+    if (s != PASTA_OK) return s;
+    CooLayout L;
+    if (!make_layout(order, dims, nnz, L)) return PASTA_EUNSUPPORTED;
+    *bytes = L.total;
+    return PASTA_OK;
+}
+
+pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz, const uint32_t *const *d_inds,
+                              const float *d_vals, void *d_workspace, size_t workspace_bytes, void *stream,
+                              pasta_coo **out)
+{
+    if (!out) return PASTA_EINVAL;
+    *out = nullptr;
+    pasta_status s = check_shape(order, dims, nnz);
+    if (s != PASTA_OK) return s;
+    if (nnz > 0) {
+        if (!d_inds || !d_vals) return PASTA_EINVAL;
+        for (uint32_t k = 0; k < order; ++k)
+            if (!d_inds[k]) return PASTA_EINVAL;
+    }
+    CooLayout L;
+    if (!make_layout(order, dims, nnz, L)) return PASTA_EUNSUPPORTED;
+    if (!d_workspace || workspace_bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
+        return PASTA_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_workspace);
+    auto at = [&](size_t off) { return reinterpret_cast<uint32_t *>(base + off); };
+
+    pasta_coo *X = new (std::nothrow) pasta_coo();
+    if (!X) return PASTA_EINVAL;
+    X->order = order;
+    X->nnz = nnz;
+    for (uint32_t k = 0; k < order; ++k) {
+        X->dims[k] = dims[k];
+        X->inds[k] = nnz ? d_inds[k] : nullptr;
+    }
+    X->vals = d_vals;
+    for (uint32_t n = 0; n < order; ++n) {
+        for (uint32_t k = 0; k < order; ++k) X->mode[n].sinds[k] = at(L.sinds[n][k]);
+        X->mode[n].svals = reinterpret_cast<float *>(base + L.svals[n]);
+        X->mode[n].perm = at(L.perm[n]);
+        X->mode[n].rowptr = at(L.rowptr[n]);
+    }
+    auto fail = [&](pasta_status e) {
+        delete X;
+        return e;
+    };
+#define HIPCHK_X(expr)                                                                                           \
+    do {                                                                                                         \
+        hipError_t e_ = (expr);                                                                                  \
+        if (e_ != hipSuccess) {                                                                                  \
+            g_last_hip_error = (int)e_;                                                                          \
+            return fail(PASTA_EHIP);                                                                             \
+        }                                                                                                        \
+    } while (0)
+
+    uint32_t *flag = at(L.flag);
+    HIPCHK_X(launch_fill_u32(flag, 0u, 1, st));
+    HIPCHK_X(launch_validate(d_inds, dims, order, nnz, flag, st));
+    uint32_t *hist = at(L.hist);
+    uint32_t *scanpart = at(L.scanpart);
+    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    for (uint32_t n = 0; n < order; ++n) {
+        auto &md = X->mode[n];
+        if (nnz > 0) {
+            const int bits = key_bits(dims[n]);
+            const int passes = (bits + kRadixBits - 1) / kRadixBits;
+            if (passes == 0) {
+                HIPCHK_X(launch_identity_sort(d_inds[n], nnz, md.sinds[n], md.perm, st));
+            } else {
+                const uint32_t *kin = d_inds[n];
+                const uint32_t *pin = nullptr;
+                for (int ps = 0; ps < passes; ++ps) {
+                    const bool last = ps == passes - 1;
+                    uint32_t *kout = last ? md.sinds[n] : (ps % 2 == 0 ? at(L.keysA) : at(L.keysB));
+                    uint32_t *pout = last ? md.perm : (ps % 2 == 0 ? at(L.permA) : at(L.permB));
+                    HIPCHK_X(launch_radix_hist(kin, nnz, ps * kRadixBits, hist, L.ntiles, st));
+                    HIPCHK_X(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
+                    HIPCHK_X(launch_radix_scatter(kin, pin, nnz, ps * kRadixBits, hist, L.ntiles, kout, pout, st));
+                    kin = kout;
+                    pin = pout;
+                }
+            }
+            HIPCHK_X(launch_permute(order, n, nnz, md.perm, d_inds, d_vals, md.sinds, md.svals, st));
+        }
+        HIPCHK_X(launch_rowptr(md.sinds[n], nnz, (uint32_t)dims[n], md.rowptr, st));
+    }
+    uint32_t host_flag = 0;
+    HIPCHK_X(hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK_X(hipStreamSynchronize(st));
+#undef HIPCHK_X
+    if (host_flag) return fail(PASTA_ERANGE);
+    *out = X;
+    return PASTA_OK;
+}
+
+pasta_status pasta_coo_destroy(pasta_coo *X)
+{
+    delete X;
+    return PASTA_OK;
+}
+
+pasta_status pasta_coo_info(const pasta_coo *X, uint32_t *order, uint64_t *nnz)
+{
+    if (!X) return PASTA_EINVAL;
+    if (order) *order = X->order;
+    if (nnz) *nnz = X->nnz;
+    return PASTA_OK;
+}
+
+pasta_status pasta_coo_mode_view(const pasta_coo *X, uint32_t mode, const uint32_t **d_perm,
+                                 const uint32_t **d_rowptr, const uint32_t **d_sorted_inds,
+                                 const float **d_sorted_vals)
+{
+    if (!X || mode >= X->order) return PASTA_EINVAL;
+    const auto &md = X->mode[mode];
+    if (d_perm) *d_perm = md.perm;
+    if (d_rowptr) *d_rowptr = md.rowptr;
+    if (d_sorted_inds)
+        for (uint32_t k = 0; k < X->order; ++k) d_sorted_inds[k] = md.sinds[k];
+    if (d_sorted_vals) *d_sorted_vals = md.svals;
+    return PASTA_OK;
+}
+
+pasta_status pasta_mttkrp_workspace_bytes(const pasta_coo *X, uint32_t mode, uint32_t rank, pasta_dtype dtype,
+                                          size_t *bytes)
+{
+    if (!X || !bytes || mode >= X->order || rank == 0) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    *bytes = mttkrp_ws_bound(X, rank, dtype);
+    return PASTA_OK;
+}
+
+pasta_status pasta_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                          uint32_t rank, uint32_t ldf, const float *d_vals_override, float alpha, float *d_out,
+                          uint32_t ldo, void *d_work, size_t work_bytes, void *stream)
+{
+    if (!X || mode >= X->order || rank == 0 || ldf < rank || ldo < rank || !d_out) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, mode);
+    if (s != PASTA_OK) return s;
+    return run_mttkrp(X, mode, d_factors, dtype, rank, ldf, d_vals_override, alpha, d_out, ldo, d_work, work_bytes,
+                      false, nullptr, static_cast<hipStream_t>(stream));
+}
+
+pasta_status pasta_mttkrp_atomic(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                                 uint32_t rank, uint32_t ldf, float *d_out, uint32_t ldo, void *stream)
+{
+    if (!X || mode >= X->order || rank == 0 || ldf < rank || ldo < rank || !d_out) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, mode);
+    if (s != PASTA_OK) return s;
+    const void *fl[kMaxOrder];
+    uint32_t nf = 0;
+    for (uint32_t k = 0; k < X->order; ++k)
+        if (k != mode) fl[nf++] = d_factors[k];
+    KernelShape sh;
+    if (!choose_shape(dtype, rank, ldf, ldo, fl, nf, nullptr, sh)) return PASTA_EUNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIPCHK(launch_zero_rows(d_out, (uint32_t)X->dims[mode], ldo, rank, st));
+    AtomicLaunch l{};
+    l.row = X->inds[mode];
+    uint32_t q = 0;
+    for (uint32_t k = 0; k < X->order; ++k) {
+        if (k == mode) continue;
+        l.idx[q] = X->inds[k];
+        l.fac[q] = d_factors[k];
+        ++q;
+    }
+    l.vals = X->vals;
+    l.out = d_out;
+    l.nnz = X->nnz;
+    l.ldf = ldf;
+    l.ldo = ldo;
+    l.rank = rank;
+    if (X->nnz > 0) HIPCHK(launch_atomic(X->order, l, dtype == PASTA_BF16, sh, st));
+    return PASTA_OK;
+}
+
+static pasta_status sample_common(const pasta_coo *X, const void *const *facs, pasta_dtype dt, uint32_t rank,
+                                  uint32_t ldf, const float *vals, float *out, double *loss_part, hipStream_t st)
+{
+    KernelShape sh;
+    if (!choose_shape(dt, rank, ldf, 4, facs, X->order, nullptr, sh)) return PASTA_EUNSUPPORTED;
+    SampleLaunch l{};
+    for (uint32_t k = 0; k < X->order; ++k) {
+        l.inds[k] = X->inds[k];
+        l.fac[k] = facs[k];
+    }
+    l.vals = vals;
+    l.out = out;
+    l.loss_part = loss_part;
+    l.nnz = X->nnz;
+    l.ldf = ldf;
+    l.rank = rank;
+    l.tiles_per_wave = kSampleTilesPerWave;
+    HIPCHK(launch_sample(X->order, l, dt == PASTA_BF16, sh, st));
+    return PASTA_OK;
+}
+
+pasta_status pasta_cp_sample(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype, uint32_t rank,
+                             uint32_t ldf, float *d_mhat, void *stream)
+{
+    if (!X || rank == 0 || ldf < rank || (!d_mhat && X->nnz > 0)) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, X->order);
+    if (s != PASTA_OK) return s;
+    if (X->nnz == 0) return PASTA_OK;
+    return sample_common(X, d_factors, dtype, rank, ldf, nullptr, d_mhat, nullptr, static_cast<hipStream_t>(stream));
+}
+
+pasta_status pasta_cp_workspace_bytes(const pasta_coo *X, uint32_t rank, pasta_dtype dtype, size_t *bytes)
+{
+    if (!X || !bytes || rank == 0) return PASTA_EINVAL;
+    (void)dtype;
+    *bytes = align_up(sample_blocks(X->nnz) * sizeof(double));
+    return PASTA_OK;
+}
+
+pasta_status pasta_cp_residual_loss(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype,
+                                    uint32_t rank, uint32_t ldf, float *d_resid, double *d_loss, void *d_work,
+                                    size_t work_bytes, void *stream)
+{
+    if (!X || rank == 0 || ldf < rank || !d_loss) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, X->order);
+    if (s != PASTA_OK) return s;
+    const size_t nb = sample_blocks(X->nnz);
+    if (!d_work || work_bytes < nb * sizeof(double) || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(d_work);
+    if (X->nnz == 0) {
+        HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(part), 0u, 2, st));
+    } else {
+        s = sample_common(X, d_factors, dtype, rank, ldf, X->vals, d_resid, part, st);
+        if (s != PASTA_OK) return s;
+    }
+    HIPCHK(launch_sum_f64(part, X->nnz == 0 ? 1u : (uint32_t)nb, d_loss, st));
+    return PASTA_OK;
+}
+
+pasta_status pasta_cp_grad_workspace_bytes(const pasta_coo *X, uint32_t rank, pasta_dtype dtype, size_t *bytes)
+{
+    if (!X || !bytes || rank == 0) return PASTA_EINVAL;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    const size_t part = mttkrp_ws_bound(X, rank, dtype);
+    // one fp64 loss partial per chunk of mode 0 (no chunk is shorter than kSub nonzeros)
+    const size_t nlp = (size_t)((X->nnz + kSub - 1) / kSub) + 1;
+    *bytes = align_up(part) + align_up(nlp * sizeof(double));
+    return PASTA_OK;
+}
+
+pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pasta_dtype dtype, uint32_t rank,
+                           uint32_t ldf, float alpha, float *const *d_grads, uint32_t ldg, double *d_loss,
+                           void *d_work, size_t work_bytes, void *stream)
+{
+    if (!X || rank == 0 || ldf < rank || ldg < rank || !d_grads) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, X->order);
+    if (s != PASTA_OK) return s;
+    for (uint32_t n = 0; n < X->order; ++n)
+        if (!d_grads[n]) return PASTA_EINVAL;
+    size_t need;
+    pasta_cp_grad_workspace_bytes(X, rank, dtype, &need);
+    if (!d_work || work_bytes < need || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t part = align_up(mttkrp_ws_bound(X, rank, dtype));
+    double *lp = reinterpret_cast<double *>(static_cast<char *>(d_work) + part);
+    for (uint32_t n = 0; n < X->order; ++n) {
+        const bool want_loss = d_loss && n == 0;
+        s = run_mttkrp(X, n, d_factors, dtype, rank, ldf, nullptr, alpha, d_grads[n], ldg, d_work, part, true,
+                       want_loss ? lp : nullptr, st);
+        if (s != PASTA_OK) return s;
+    }
+    if (d_loss) {
+        if (X->nnz == 0) {
+            HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(lp), 0u, 2, st));
+            HIPCHK(launch_sum_f64(lp, 1u, d_loss, st));
+        } else {
+            // mode 0's chunk count for the shape it ran with
+            const void *fl[kMaxOrder];
+            for (uint32_t k = 0; k < X->order; ++k) fl[k] = d_factors[k];
+            KernelShape sh;
+            choose_shape(dtype, rank, ldf, ldg, fl, X->order, d_grads[0], sh);
+            MttkrpPlan p;
+            plan_mttkrp(X, rank, sh, p);
+            HIPCHK(launch_sum_f64(lp, p.nchunks, d_loss, st));
+        }
+    }
+    return PASTA_OK;
+}
+
+pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_t count, void *stream)
+{
+    if (count > 0 && (!d_src || !d_dst)) return PASTA_EINVAL;
+    HIPCHK(launch_cast_bf16(d_src, d_dst, count, static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream)
+{
+    if (count > 0 && (!d_x || !d_alpha)) return PASTA_EINVAL;
+    HIPCHK(launch_scale(d_x, count, d_alpha, static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_adam_step(float *d_param, const float *d_grad, float *d_m, float *d_v, uint16_t *d_shadow_bf16,
+                             uint64_t count, float lr, float beta1, float beta2, float eps, uint32_t step,
+                             void *stream)
+{
+    if (count > 0 && (!d_param || !d_grad || !d_m || !d_v)) return PASTA_EINVAL;
+    if (step == 0 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return PASTA_EINVAL;
+    HIPCHK(launch_adam(d_param, d_grad, d_m, d_v, d_shadow_bf16, count, lr, beta1, beta2, eps, step,
+                       static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+const char *pasta_status_str(pasta_status s)
+{
+    switch (s) {
+    case PASTA_OK: return "ok";
+    case PASTA_EINVAL: return "invalid argument";
+    case PASTA_ERANGE: return "coordinate out of range";
+    case PASTA_EUNSUPPORTED: return "unsupported order, rank, dtype or alignment";
+    case PASTA_EWORKSPACE: return "workspace too small or misaligned";
+    case PASTA_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+int pasta_last_hip_error(void) { return g_last_hip_error; }
+
+}  // extern "C"

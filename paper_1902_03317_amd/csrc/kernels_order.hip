@@ -1,0 +1,501 @@
+// Order-specialised gfx950 kernels: mode-n MTTKRP over the mode-sorted
+// stream, the sampled CP model, and the atomic variant. This file is
+// compiled once per order with PASTA_NM1 = order - 1 (the number of factor
+// rows gathered per nonzero), so every loop over modes is unrolled.
+//
+// MTTKRP (Section 4.6, eq. mttkrp-init; Alg. 6 of Section 5.2, generalised
+// to order N and any mode n): out[i,:] = alpha * sum_{m: i_n(m)=i} x_m *
+// (U^(k1)[i_k1(m),:] * ... * U^(kN-1)[i_kN-1(m),:]) (Hadamard product).
+//
+// Work split. The nonzeros, sorted by i_n, are cut into chunks of
+// C = G * sub consecutive nonzeros, one chunk per wave64. A wave is G lane
+// groups of L lanes; lane j of a group owns elements j*VEC .. j*VEC+VEC-1 of
+// the R-wide rows (16-byte gathers). Group g walks its own contiguous run of
+// `sub` nonzeros and keeps the running row sum in registers while i_n does
+// not change, so a row that starts and ends inside the run is finished
+// there and stored once with a plain store. At the end of the chunk the
+// first and last rows of the G runs are joined by a segmented scan across
+// the groups (cross-lane shuffles); joined rows that stay inside the chunk
+// are stored, and a row that crosses a chunk edge leaves a partial in a
+// scratch slot for the fixup kernel. No atomics, and the summation order is
+// fixed, so results are bitwise reproducible.
+#include "common.h"
+
+#ifndef PASTA_NM1
+#error "compile with -DPASTA_NM1=<order-1>"
+#endif
+
+namespace pasta {
+namespace {
+
+constexpr int NM1 = PASTA_NM1;
+// Nonzeros a group handles per step; their NM1 gathers are issued together.
+constexpr int kStep = NM1 <= 2 ? 8 : (NM1 <= 4 ? 4 : 2);
+
+struct MttkrpArgs {
+    const uint32_t *row;
+    const uint32_t *idx[NM1];
+    const void *fac[NM1];
+    const void *facn;
+    const float *vals;
+    const uint32_t *perm;
+    float *out;
+    float *part;
+    double *loss_part;
+    uint64_t nnz;
+    uint32_t ldf, ldo, ldp, rank, sub, nchunks;
+    float alpha;
+};
+
+template <typename FT, int VEC, int L, bool STRIDED, bool FUSED>
+__global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
+{
+    constexpr int G = kWave / L;
+    constexpr int U = kStep;
+    constexpr int EPL = L >= U ? 1 : U / L;  // entries each lane loads per step
+    using S = Slice<FT, VEC, STRIDED>;
+    using Packed = typename S::Packed;
+
+    const int lane = threadIdx.x & 63;
+    const uint32_t chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (chunk >= a.nchunks) return;  // whole wave leaves together
+    const int g = lane / L, j = lane % L;
+    const int gbase = lane & ~(L - 1);
+    const uint64_t C = (uint64_t)a.sub * G;
+    const uint64_t c0 = (uint64_t)chunk * C;
+    const uint64_t c1 = c0 + C < a.nnz ? c0 + C : a.nnz;
+    const uint64_t s0 = c0 + (uint64_t)g * a.sub < c1 ? c0 + (uint64_t)g * a.sub : c1;
+    const uint64_t s1 = s0 + a.sub < c1 ? s0 + a.sub : c1;
+    const bool lane_on = S::active(j, a.rank);
+
+    float acc[VEC], head[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = head[e] = 0.0f;
+    float rowfac[VEC];  // fused: U^(n) slice of the current row
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rowfac[e] = 0.0f;
+    double loss = 0.0;
+    uint32_t cur = kNoRow, hrow = kNoRow;
+    bool multi = false;  // this group has already closed its first row
+
+    for (uint64_t p = s0; p < s1; p += U) {
+        const uint32_t navail = (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
+        // coalesced loads of U entries spread over the group's lanes
+        uint32_t lr[EPL], li[EPL][NM1];
+        float lv[EPL];
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+            const int e = j + L * t;
+            lr[t] = 0;
+            lv[t] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < NM1; ++k) li[t][k] = 0;
+            if (e < U && (uint32_t)e < navail) {
+                const uint64_t q = p + e;
+                lr[t] = a.row[q];
+#pragma unroll
+                for (int k = 0; k < NM1; ++k) li[t][k] = a.idx[k][q];
+                lv[t] = a.perm ? a.vals[a.perm[q]] : a.vals[q];
+            }
+        }
+        // broadcast each entry to the group and issue all its gathers
+        uint32_t ru[U];
+        float vu[U];
+        Packed gp[U][NM1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int src = gbase | (u % L);
+            ru[u] = (uint32_t)__shfl((int)lr[u / L], src);
+            vu[u] = __shfl(lv[u / L], src);
+#pragma unroll
+            for (int k = 0; k < NM1; ++k) {
+                const uint32_t iu = (uint32_t)__shfl((int)li[u / L][k], src);
+                if ((uint32_t)u < navail && lane_on) {
+                    S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, j, a.rank, gp[u][k]);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < S::kWords; ++w) gp[u][k].w[w] = 0u;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if ((uint32_t)u >= navail) break;
+            float q[VEC];
+            S::unpack(gp[u][0], q);
+#pragma unroll
+            for (int k = 1; k < NM1; ++k) {
+                float t[VEC];
+                S::unpack(gp[u][k], t);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+            }
+            if (ru[u] != cur) {
+                if (cur != kNoRow) {
+                    if (!multi) {  // the run's first row may continue in earlier runs: keep it
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) head[e] = acc[e];
+                        hrow = cur;
+                        multi = true;
+                    } else if (lane_on) {  // a row inside the run: complete, store it
+                        store_slice<VEC, STRIDED>(a.out + (uint64_t)cur * a.ldo, j, a.rank, acc, a.alpha);
+                    }
+                }
+                cur = ru[u];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+                if constexpr (FUSED) {
+                    if (lane_on) S::load_f(static_cast<const FT *>(a.facn) + (uint64_t)cur * a.ldf, j, a.rank, rowfac);
+                }
+            }
+            float w = vu[u];
+            if constexpr (FUSED) {  // residual of the CP model at this nonzero
+                float d = 0.0f;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) d += rowfac[e] * q[e];
+                d = group_sum<L>(d);
+                w = d - vu[u];
+                if (j == 0) loss += 0.5 * (double)w * (double)w;
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += w * q[e];
+        }
+    }
+
+    // ---- join the runs' edge rows across the G groups of the wave ----
+    const uint32_t first = multi ? hrow : cur;  // the run's first row (kNoRow if empty)
+    uint32_t prev_last = (uint32_t)__shfl_up((int)cur, L);
+    if (g == 0) prev_last = kNoRow;
+    const bool cont = cur != kNoRow && first == prev_last;  // continues the previous run's last row
+    // segmented inclusive scan of the last-row sums; only single-row runs pass a sum on
+    bool seg_start = !(cont && !multi);
+    float carry[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) carry[e] = acc[e];
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const bool ps = __shfl_up((int)seg_start, d * L) != 0;
+        float pv[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) pv[e] = __shfl_up(carry[e], d * L);
+        if (g >= d && !seg_start) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) carry[e] += pv[e];
+        }
+        if (g >= d) seg_start = seg_start || ps;
+    }
+    float prev_carry[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) prev_carry[e] = __shfl_up(carry[e], L);
+    int next_cont = __shfl_down((int)cont, L);
+    if (g == G - 1) next_cont = 0;
+
+    // chunk-edge classification
+    const uint32_t cfirst = a.row[c0];
+    const uint32_t clast = a.row[c1 - 1];
+    const bool before = c0 > 0 && a.row[c0 - 1] == cfirst;
+    const bool after = c1 < a.nnz && a.row[c1] == clast;
+    auto emit = [&](uint32_t r, const float (&v)[VEC]) {
+        if (!lane_on) return;
+        if (r == cfirst && before)
+            store_slice<VEC, STRIDED>(a.part + (uint64_t)(2 * (uint64_t)chunk) * a.ldp, j, a.rank, v, 1.0f);
+        else if (r == clast && after)
+            store_slice<VEC, STRIDED>(a.part + (uint64_t)(2 * (uint64_t)chunk + 1) * a.ldp, j, a.rank, v, 1.0f);
+        else
+            store_slice<VEC, STRIDED>(a.out + (uint64_t)r * a.ldo, j, a.rank, v, a.alpha);
+    };
+    if (multi) {  // first row closed inside this run; add what earlier runs carried
+        if (cont) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) head[e] += prev_carry[e];
+        }
+        emit(hrow, head);
+    }
+    if (cur != kNoRow && !next_cont) emit(cur, carry);
+
+    if constexpr (FUSED) {
+        if (a.loss_part) {
+            const double tot = wave_sum_f64(loss);
+            if (lane == 0) a.loss_part[chunk] = tot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sampled CP model: mhat_m = sum_r prod_k U^(k)[i_k(m), r], caller order.
+// A wave takes 64 consecutive nonzeros at a time (coalesced index loads, one
+// per lane); group g handles the L of them held by its own lanes.
+// ---------------------------------------------------------------------------
+struct SampleArgs {
+    const uint32_t *inds[NM1 + 1];
+    const void *fac[NM1 + 1];
+    const float *vals;
+    float *out;
+    double *loss_part;
+    uint64_t nnz;
+    uint32_t ldf, rank, tiles_per_wave;
+};
+
+template <typename FT, int VEC, int L, bool STRIDED>
+__global__ __launch_bounds__(256) void cp_sample_kernel(const SampleArgs a)
+{
+    constexpr int N = NM1 + 1;
+    constexpr int B = L < 8 ? L : 8;  // entries per batch
+    using S = Slice<FT, VEC, STRIDED>;
+    using Packed = typename S::Packed;
+    __shared__ double lds[4];
+    const int lane = threadIdx.x & 63;
+    const int j = lane % L;
+    const int gbase = lane & ~(L - 1);
+    const bool lane_on = S::active(j, a.rank);
+    const uint64_t wave_id = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    double loss = 0.0;
+    for (uint32_t tt = 0; tt < a.tiles_per_wave; ++tt) {
+        const uint64_t base = (wave_id * a.tiles_per_wave + tt) * 64;
+        if (base >= a.nnz) break;
+        const uint64_t m = base + lane;
+        const bool on = m < a.nnz;
+        uint32_t li[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) li[k] = on ? a.inds[k][m] : 0u;
+        float mine = 0.0f;
+#pragma unroll
+        for (int b0 = 0; b0 < L; b0 += B) {
+            Packed gp[B][N];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int src = gbase | (b0 + u);
+                const bool src_on = base + (uint64_t)src < a.nnz;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const uint32_t iu = (uint32_t)__shfl((int)li[k], src);
+                    if (src_on && lane_on) {
+                        S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, j, a.rank, gp[u][k]);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < S::kWords; ++w) gp[u][k].w[w] = 0u;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                float q[VEC];
+                S::unpack(gp[u][0], q);
+#pragma unroll
+                for (int k = 1; k < N; ++k) {
+                    float t[VEC];
+                    S::unpack(gp[u][k], t);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+                }
+                float s = 0.0f;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) s += q[e];
+                s = group_sum<L>(s);
+                if (j == b0 + u) mine = s;
+            }
+        }
+        if (on) {
+            if (a.vals) {
+                const float r = mine - a.vals[m];
+                if (a.out) a.out[m] = r;
+                loss += 0.5 * (double)r * (double)r;
+            } else {
+                a.out[m] = mine;
+            }
+        }
+    }
+    if (a.loss_part) {
+        const double w = wave_sum_f64(loss);
+        if (lane == 0) lds[threadIdx.x >> 6] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) a.loss_part[blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The parallel-with-atomics form of Section 5.3 on the GPU: nonzeros in
+// caller order, every lane group adds its nonzero's product row into the
+// output with fp32 atomics (output zeroed first).
+// ---------------------------------------------------------------------------
+struct AtomicArgs {
+    const uint32_t *row;
+    const uint32_t *idx[NM1];
+    const void *fac[NM1];
+    const float *vals;
+    float *out;
+    uint64_t nnz;
+    uint32_t ldf, ldo, rank;
+};
+
+template <typename FT, int VEC, int L, bool STRIDED>
+__global__ __launch_bounds__(256) void mttkrp_atomic_kernel(const AtomicArgs a)
+{
+    constexpr int G = kWave / L;
+    using S = Slice<FT, VEC, STRIDED>;
+    const int lane = threadIdx.x & 63;
+    const int g = lane / L, j = lane % L;
+    if (!S::active(j, a.rank)) return;
+    const uint64_t nwaves = (uint64_t)gridDim.x * 4;
+    for (uint64_t m = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * G + g; m < a.nnz; m += nwaves * G) {
+        float q[VEC];
+        S::load_f(static_cast<const FT *>(a.fac[0]) + (uint64_t)a.idx[0][m] * a.ldf, j, a.rank, q);
+#pragma unroll
+        for (int k = 1; k < NM1; ++k) {
+            float t[VEC];
+            S::load_f(static_cast<const FT *>(a.fac[k]) + (uint64_t)a.idx[k][m] * a.ldf, j, a.rank, t);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+        }
+        const float x = a.vals[m];
+        float *o = a.out + (uint64_t)a.row[m] * a.ldo;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const uint32_t c = STRIDED ? (uint32_t)j + 64u * e : (uint32_t)(j * VEC + e);
+            if (c < a.rank) atomicAdd(o + c, x * q[e]);
+        }
+    }
+}
+
+unsigned clamp_grid(uint64_t g, uint64_t cap)
+{
+    if (g < 1) g = 1;
+    return (unsigned)(g > cap ? cap : g);
+}
+
+template <typename FT, int VEC, int L, bool STRIDED>
+hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
+    if (fused)
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, true><<<grid, 256, 0, st>>>(args);
+    else
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false><<<grid, 256, 0, st>>>(args);
+    return hipGetLastError();
+}
+
+template <typename FT, int VEC, int L, bool STRIDED>
+hipError_t run_sample(const SampleArgs &args, hipStream_t st)
+{
+    const uint64_t tiles = (args.nnz + 63) / 64;
+    const uint64_t waves = (tiles + args.tiles_per_wave - 1) / args.tiles_per_wave;
+    cp_sample_kernel<FT, VEC, L, STRIDED><<<clamp_grid((waves + 3) / 4, 1u << 30), 256, 0, st>>>(args);
+    return hipGetLastError();
+}
+
+template <typename FT, int VEC, int L, bool STRIDED>
+hipError_t run_atomic(const AtomicArgs &args, hipStream_t st)
+{
+    constexpr int G = kWave / L;
+    const uint64_t waves = (args.nnz + G - 1) / G;
+    mttkrp_atomic_kernel<FT, VEC, L, STRIDED><<<clamp_grid((waves + 3) / 4, 16384), 256, 0, st>>>(args);
+    return hipGetLastError();
+}
+
+// Dispatch on (dtype, shape): contiguous fp32 float4 / bf16 8-wide slices
+// with L in {1,2,4,8,16}, or the strided generic path (L = 64, 4 per lane).
+template <template <typename, int, int, bool> class F, typename Args, typename... X>
+hipError_t dispatch(const Args &args, bool bf16, KernelShape s, hipStream_t st, X... extra)
+{
+    if (s.strided) {
+        if (bf16) return F<uint16_t, 4, 64, true>::run(args, st, extra...);
+        return F<float, 4, 64, true>::run(args, st, extra...);
+    }
+#define PASTA_CASE(LL)                                                                                           \
+    case LL:                                                                                                     \
+        if (bf16) return F<uint16_t, 8, LL, false>::run(args, st, extra...);                                   \
+        return F<float, 4, LL, false>::run(args, st, extra...);
+    switch (s.lanes) {
+        PASTA_CASE(1)
+        PASTA_CASE(2)
+        PASTA_CASE(4)
+        PASTA_CASE(8)
+        PASTA_CASE(16)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef PASTA_CASE
+}
+
+template <typename FT, int VEC, int L, bool STRIDED>
+struct MttkrpRun {
+    static hipError_t run(const MttkrpArgs &a, hipStream_t st, bool fused) { return run_mttkrp<FT, VEC, L, STRIDED>(a, fused, st); }
+};
+template <typename FT, int VEC, int L, bool STRIDED>
+struct SampleRun {
+    static hipError_t run(const SampleArgs &a, hipStream_t st) { return run_sample<FT, VEC, L, STRIDED>(a, st); }
+};
+template <typename FT, int VEC, int L, bool STRIDED>
+struct AtomicRun {
+    static hipError_t run(const AtomicArgs &a, hipStream_t st) { return run_atomic<FT, VEC, L, STRIDED>(a, st); }
+};
+
+}  // namespace
+
+#define PASTA_CAT2(a, b) a##b
+#define PASTA_CAT(a, b) PASTA_CAT2(a, b)
+
+hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool bf16, KernelShape s, bool fused,
+                                                    hipStream_t st)
+{
+    if (l.nchunks == 0) return hipSuccess;
+    MttkrpArgs a{};
+    a.row = l.row;
+    for (int k = 0; k < NM1; ++k) {
+        a.idx[k] = l.idx[k];
+        a.fac[k] = l.fac[k];
+    }
+    a.facn = l.facn;
+    a.vals = l.vals;
+    a.perm = l.perm;
+    a.out = l.out;
+    a.part = l.part;
+    a.loss_part = l.loss_part;
+    a.nnz = l.nnz;
+    a.ldf = l.ldf;
+    a.ldo = l.ldo;
+    a.ldp = l.ldp;
+    a.rank = l.rank;
+    a.sub = l.sub;
+    a.nchunks = l.nchunks;
+    a.alpha = l.alpha;
+    return dispatch<MttkrpRun>(a, bf16, s, st, fused);
+}
+
+hipError_t PASTA_CAT(launch_sample_nm1_, PASTA_NM1)(const SampleLaunch &l, bool bf16, KernelShape s, hipStream_t st)
+{
+    if (l.nnz == 0) return hipSuccess;
+    SampleArgs a{};
+    for (int k = 0; k <= NM1; ++k) {
+        a.inds[k] = l.inds[k];
+        a.fac[k] = l.fac[k];
+    }
+    a.vals = l.vals;
+    a.out = l.out;
+    a.loss_part = l.loss_part;
+    a.nnz = l.nnz;
+    a.ldf = l.ldf;
+    a.rank = l.rank;
+    a.tiles_per_wave = l.tiles_per_wave;
+    return dispatch<SampleRun>(a, bf16, s, st);
+}
+
+hipError_t PASTA_CAT(launch_atomic_nm1_, PASTA_NM1)(const AtomicLaunch &l, bool bf16, KernelShape s, hipStream_t st)
+{
+    if (l.nnz == 0) return hipSuccess;
+    AtomicArgs a{};
+    a.row = l.row;
+    for (int k = 0; k < NM1; ++k) {
+        a.idx[k] = l.idx[k];
+        a.fac[k] = l.fac[k];
+    }
+    a.vals = l.vals;
+    a.out = l.out;
+    a.nnz = l.nnz;
+    a.ldf = l.ldf;
+    a.ldo = l.ldo;
+    a.rank = l.rank;
+    return dispatch<AtomicRun>(a, bf16, s, st);
+}
+
+}  // namespace pasta
