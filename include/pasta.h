@@ -160,6 +160,13 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
  * d_dst[i] = bf16(d_src[i]) for i < count, bf16 given as uint16 bits. */
 pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_t count, void *stream);
 
+/* Measurement hook: the next MTTKRP main kernel that this thread launches
+ * (from pasta_mttkrp or the first mode of pasta_cp_grad) records ev_start
+ * (a hipEvent_t) on its stream right before the launch and ev_stop right
+ * after it, so their elapsed time is that kernel alone. The pair is used
+ * once and then disarmed; NULL disarms. Calls with nnz = 0 leave it armed. */
+pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop);
+
 /* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
  * derivative held on the device (no host round trip). */
 pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream);

@@ -45,6 +45,7 @@ SIGNATURES = {
     "pasta_cp_grad": [P, P, ctypes.c_int, U32, U32, F32, P, U32, P, P, SZ, P],
     "pasta_cast_f32_to_bf16": [P, P, U64, P],
     "pasta_scale_f32": [P, U64, P, P],
+    "pasta_arm_kernel_events": [P, P],
     "pasta_adam_step": [P, P, P, P, P, U64, F32, F32, F32, F32, U32, P],
 }
 

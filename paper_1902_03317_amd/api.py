@@ -31,7 +31,8 @@ class Coo:
     mode's index, in a workspace this object owns.
     """
 
-    def __init__(self, dims: Sequence[int], inds, vals: torch.Tensor, stream=None):
+    def __init__(self, dims: Sequence[int], inds, vals: torch.Tensor, stream=None,
+                 workspace: Optional[torch.Tensor] = None):
         self.dims = tuple(int(d) for d in dims)
         self.order = len(self.dims)
         rows = list(inds) if not isinstance(inds, torch.Tensor) else [inds[k] for k in range(inds.shape[0])]
@@ -52,7 +53,10 @@ class Coo:
         nbytes = ctypes.c_size_t()
         check(lib.pasta_coo_workspace_bytes(self.order, self._dims_c, self.nnz, ctypes.byref(nbytes)),
               "pasta_coo_workspace_bytes")
-        self.workspace = _scratch(nbytes.value, self.device)
+        if workspace is not None and workspace.dtype == torch.uint8 and workspace.numel() >= nbytes.value:
+            self.workspace = workspace
+        else:
+            self.workspace = _scratch(nbytes.value, self.device)
         self._ind_ptrs = ptr_array([r.data_ptr() for r in self.inds])
         h = ctypes.c_void_p()
         check(lib.pasta_coo_create(self.order, self._dims_c, self.nnz, self._ind_ptrs, self.vals.data_ptr(),
@@ -108,6 +112,13 @@ def _factor_args(X: Coo, factors: Sequence[Optional[torch.Tensor]], skip: Option
         raise TypeError("factors must be float32 or bfloat16")
     ptrs = ptr_array([0 if f is None else f.data_ptr() for f in factors])
     return ptrs, _DT[ref.dtype], int(ref.shape[1]), int(max(ref.stride(0), ref.shape[1]))
+
+
+def coo_workspace_bytes(dims: Sequence[int], nnz: int) -> int:
+    d = (ctypes.c_uint64 * len(dims))(*[int(x) for x in dims])
+    n = ctypes.c_size_t()
+    check(lib.pasta_coo_workspace_bytes(len(dims), d, int(nnz), ctypes.byref(n)), "pasta_coo_workspace_bytes")
+    return n.value
 
 
 def mttkrp_workspace_bytes(X: Coo, mode: int, rank: int, dtype=torch.float32) -> int:

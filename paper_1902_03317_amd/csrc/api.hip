@@ -27,6 +27,8 @@ struct pasta_coo {
 namespace {
 
 thread_local int g_last_hip_error = 0;
+// events armed by pasta_arm_kernel_events for the next main kernel launch on this thread
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
 #define HIPCHK(expr)                                                                                             \
     do {                                                                                                         \
@@ -279,7 +281,13 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     l.sub = p.sub;
     l.nchunks = p.nchunks;
     l.alpha = alpha;
-    if (X->nnz > 0) HIPCHK(launch_mttkrp(X->order, l, dt == PASTA_BF16, s, fused, st));
+    if (X->nnz > 0) {
+        hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+        g_ev_start = g_ev_stop = nullptr;
+        if (e0) HIPCHK(hipEventRecord(e0, st));
+        HIPCHK(launch_mttkrp(X->order, l, dt == PASTA_BF16, s, fused, st));
+        if (e1) HIPCHK(hipEventRecord(e1, st));
+    }
     HIPCHK(launch_fixup(md.rowptr, (uint32_t)X->dims[mode], l.part, p.ldp, out, ldo, rank, p.chunk, alpha, s, st));
     return PASTA_OK;
 }
@@ -594,6 +602,13 @@ pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_
 {
     if (count > 0 && (!d_src || !d_dst)) return PASTA_EINVAL;
     HIPCHK(launch_cast_bf16(d_src, d_dst, count, static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop)
+{
+    g_ev_start = static_cast<hipEvent_t>(ev_start);
+    g_ev_stop = static_cast<hipEvent_t>(ev_stop);
     return PASTA_OK;
 }
 

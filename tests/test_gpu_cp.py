@@ -89,9 +89,9 @@ def test_cp_grad_order5_and_residual_path_agree():
 
 
 def _head_block():
-    """The fully observed 30x20x10 head block of the 50Kx40Kx30K Zipf tensor's recipe,
-    drawn at reduced nonzero count (its head cells are all present)."""
-    sp = synth.CONFIGS[4].scaled(2_000_000)
+    """The 30x20x10 head block of the full 50Kx40Kx30K / 50M-nonzero Zipf(1.1) tensor:
+    at that size every one of its 6000 cells is present."""
+    sp = synth.CONFIGS[4]
     coo = synth.make_coo(sp)
     blk = synth.head_block(coo, sp, (30, 20, 10))
     return sp, blk
