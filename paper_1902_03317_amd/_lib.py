@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpasta.so")
+# PASTA_LIBRARY may name another build of the same library (e.g. one compiled
+# with different tuning parameters); by default the in-tree build is used.
+LIB_PATH = os.environ.get("PASTA_LIBRARY") or os.path.join(HERE, "libpasta.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1902_03317_amd.build` "

@@ -40,7 +40,10 @@ thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
     } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr uint32_t kSub = 256;            // nonzeros per lane group per chunk
+#ifndef PASTA_SUB
+#define PASTA_SUB 256
+#endif
+constexpr uint32_t kSub = PASTA_SUB;      // nonzeros per lane group per chunk
 constexpr uint32_t kSampleTilesPerWave = 16;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -48,7 +51,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct CooLayout {
     size_t sinds[kMaxOrder][kMaxOrder];
     size_t svals[kMaxOrder], perm[kMaxOrder], rowptr[kMaxOrder];
-    size_t flag, keysA, permA, keysB, permB, hist, scanpart;
+    size_t flag, hist, scanpart;
+    size_t tmp[2][kMaxOrder + 2];  // two ping-pong sets: key, permutation, N-1 indices, values
     size_t total;
     uint32_t ntiles;
 };
@@ -79,14 +83,14 @@ bool make_layout(uint32_t N, const uint64_t *dims, uint64_t nnz, CooLayout &L)
     }
     L.flag = off;
     checked_add(off, 4);
-    L.keysA = off;
-    checked_add(off, m4);
-    L.permA = off;
-    checked_add(off, m4);
-    L.keysB = off;
-    checked_add(off, m4);
-    L.permB = off;
-    checked_add(off, m4);
+    // ping-pong buffers are needed only when some mode sorts in more than one pass
+    bool multi_pass = false;
+    for (uint32_t n = 0; n < N; ++n) multi_pass = multi_pass || dims[n] > (1ull << kRadixBits);
+    for (int set = 0; set < 2; ++set)
+        for (uint32_t a = 0; a < N + 2; ++a) {
+            L.tmp[set][a] = off;
+            if (multi_pass && !checked_add(off, m4)) return false;
+        }
     L.ntiles = (uint32_t)std::max<uint64_t>(1, (nnz + kSortTile - 1) / kSortTile);
     const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
     L.hist = off;
@@ -367,23 +371,41 @@ pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz
         if (nnz > 0) {
             const int bits = key_bits(dims[n]);
             const int passes = (bits + kRadixBits - 1) / kRadixBits;
-            if (passes == 0) {
+            if (passes == 0) {  // a mode of size 1: the order is the caller's
                 HIPCHK_X(launch_identity_sort(d_inds[n], nnz, md.sinds[n], md.perm, st));
+                HIPCHK_X(launch_permute(order, n, nnz, md.perm, d_inds, d_vals, md.sinds, md.svals, st));
             } else {
+                // inputs of the first pass: the caller's arrays, identity permutation
                 const uint32_t *kin = d_inds[n];
-                const uint32_t *pin = nullptr;
+                SortPayload pl{};
+                pl.in[0] = nullptr;
+                int cnt = 1;
+                for (uint32_t k = 0; k < order; ++k)
+                    if (k != n) pl.in[cnt++] = d_inds[k];
+                pl.in[cnt++] = reinterpret_cast<const uint32_t *>(d_vals);
+                pl.count = cnt;
                 for (int ps = 0; ps < passes; ++ps) {
                     const bool last = ps == passes - 1;
-                    uint32_t *kout = last ? md.sinds[n] : (ps % 2 == 0 ? at(L.keysA) : at(L.keysB));
-                    uint32_t *pout = last ? md.perm : (ps % 2 == 0 ? at(L.permA) : at(L.permB));
+                    uint32_t *kout;
+                    if (last) {
+                        kout = md.sinds[n];
+                        int c = 1;
+                        pl.out[0] = md.perm;
+                        for (uint32_t k = 0; k < order; ++k)
+                            if (k != n) pl.out[c++] = md.sinds[k];
+                        pl.out[c++] = reinterpret_cast<uint32_t *>(md.svals);
+                    } else {
+                        const int set = ps & 1;
+                        kout = at(L.tmp[set][0]);
+                        for (int c = 0; c < cnt; ++c) pl.out[c] = at(L.tmp[set][c + 1]);
+                    }
                     HIPCHK_X(launch_radix_hist(kin, nnz, ps * kRadixBits, hist, L.ntiles, st));
                     HIPCHK_X(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
-                    HIPCHK_X(launch_radix_scatter(kin, pin, nnz, ps * kRadixBits, hist, L.ntiles, kout, pout, st));
+                    HIPCHK_X(launch_radix_scatter(kin, nnz, ps * kRadixBits, hist, L.ntiles, kout, pl, st));
                     kin = kout;
-                    pin = pout;
+                    for (int c = 0; c < cnt; ++c) pl.in[c] = pl.out[c];
                 }
             }
-            HIPCHK_X(launch_permute(order, n, nnz, md.perm, d_inds, d_vals, md.sinds, md.svals, st));
         }
         HIPCHK_X(launch_rowptr(md.sinds[n], nnz, (uint32_t)dims[n], md.rowptr, st));
     }

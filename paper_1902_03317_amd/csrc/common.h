@@ -204,9 +204,15 @@ hipError_t launch_validate(const uint32_t *const *inds, const uint64_t *dims, ui
                            uint32_t *flag, hipStream_t st);
 hipError_t launch_radix_hist(const uint32_t *keys, uint64_t n, int shift, uint32_t *hist, uint32_t ntiles,
                              hipStream_t st);
-hipError_t launch_radix_scatter(const uint32_t *keys_in, const uint32_t *perm_in, uint64_t n, int shift,
-                                const uint32_t *offsets, uint32_t ntiles, uint32_t *keys_out, uint32_t *perm_out,
-                                hipStream_t st);
+// Arrays that travel with the sort key: [0] the permutation (in[0] == NULL
+// means the identity), then the other modes' indices and the values' bits.
+struct SortPayload {
+    const uint32_t *in[kMaxOrder + 1];
+    uint32_t *out[kMaxOrder + 1];
+    int count;
+};
+hipError_t launch_radix_scatter(const uint32_t *keys_in, uint64_t n, int shift, const uint32_t *offsets,
+                                uint32_t ntiles, uint32_t *keys_out, const SortPayload &pl, hipStream_t st);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
                                  hipStream_t st);
 uint64_t scan_partials_count(uint64_t n);

@@ -30,7 +30,11 @@ namespace {
 
 constexpr int NM1 = PASTA_NM1;
 // Nonzeros a group handles per step; their NM1 gathers are issued together.
+#ifdef PASTA_STEP
+constexpr int kStep = PASTA_STEP;
+#else
 constexpr int kStep = NM1 <= 2 ? 8 : (NM1 <= 4 ? 4 : 2);
+#endif
 
 struct MttkrpArgs {
     const uint32_t *row;
@@ -47,7 +51,7 @@ struct MttkrpArgs {
     float alpha;
 };
 
-template <typename FT, int VEC, int L, bool STRIDED, bool FUSED>
+template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR>
 __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;
@@ -78,26 +82,45 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     uint32_t cur = kNoRow, hrow = kNoRow;
     bool multi = false;  // this group has already closed its first row
 
-    for (uint64_t p = s0; p < s1; p += U) {
-        const uint32_t navail = (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
-        // coalesced loads of U entries spread over the group's lanes
-        uint32_t lr[EPL], li[EPL][NM1];
-        float lv[EPL];
+    // Index stream, software-pipelined two steps ahead: the loads for step
+    // i + 2 are issued after the gathers of step i. Loads return in order, so
+    // waiting for the gathers of a step never waits for the prefetch, and a
+    // step's gathers never wait for a fresh trip to memory for their indices.
+    // The prefetch is branch-free (indices clamped into the stream) so the
+    // compiler can count the loads in flight exactly. With a value override
+    // the permutation is prefetched and the value itself gathered one step
+    // ahead of its use.
+    struct Entries {
+        uint32_t r[EPL], i[EPL][NM1];
+        float v[EPL];
+    };
+    const uint64_t last = a.nnz - 1;
+    auto load_entries = [&](uint64_t p, Entries &E) {
 #pragma unroll
         for (int t = 0; t < EPL; ++t) {
-            const int e = j + L * t;
-            lr[t] = 0;
-            lv[t] = 0.0f;
+            const uint64_t q0 = p + (uint64_t)(j + L * t);
+            const uint64_t q = q0 < last ? q0 : last;
+            E.r[t] = a.row[q];
 #pragma unroll
-            for (int k = 0; k < NM1; ++k) li[t][k] = 0;
-            if (e < U && (uint32_t)e < navail) {
-                const uint64_t q = p + e;
-                lr[t] = a.row[q];
-#pragma unroll
-                for (int k = 0; k < NM1; ++k) li[t][k] = a.idx[k][q];
-                lv[t] = a.perm ? a.vals[a.perm[q]] : a.vals[q];
-            }
+            for (int k = 0; k < NM1; ++k) E.i[t][k] = a.idx[k][q];
+            if constexpr (OVR)
+                E.v[t] = __uint_as_float(a.perm[q]);
+            else
+                E.v[t] = a.vals[q];
         }
+    };
+    auto resolve_values = [&](Entries &E) {
+        if constexpr (OVR) {
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) E.v[t] = a.vals[__float_as_uint(E.v[t])];
+        }
+    };
+    // One step of U entries: gathers for E0, values of E1, prefetch into E2.
+    // The loop below is unrolled three times with the buffers' roles rotated,
+    // so no register holding a load in flight is ever copied (a copy would
+    // have to wait for the load).
+    auto step = [&](Entries &E0, Entries &E1, Entries &E2, uint64_t p) {
+        const uint32_t navail = (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
         // broadcast each entry to the group and issue all its gathers
         uint32_t ru[U];
         float vu[U];
@@ -105,11 +128,11 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int src = gbase | (u % L);
-            ru[u] = (uint32_t)__shfl((int)lr[u / L], src);
-            vu[u] = __shfl(lv[u / L], src);
+            ru[u] = (uint32_t)__shfl((int)E0.r[u / L], src);
+            vu[u] = __shfl(E0.v[u / L], src);
 #pragma unroll
             for (int k = 0; k < NM1; ++k) {
-                const uint32_t iu = (uint32_t)__shfl((int)li[u / L][k], src);
+                const uint32_t iu = (uint32_t)__shfl((int)E0.i[u / L][k], src);
                 if ((uint32_t)u < navail && lane_on) {
                     S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, j, a.rank, gp[u][k]);
                 } else {
@@ -118,6 +141,9 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                 }
             }
         }
+        __builtin_amdgcn_sched_barrier(0);  // the prefetch goes out after this step's gathers
+        resolve_values(E1);
+        load_entries(p + 2 * U, E2);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if ((uint32_t)u >= navail) break;
@@ -160,6 +186,18 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[e] += w * q[e];
         }
+    };
+    Entries e0, e1, e2;
+    load_entries(s0, e0);
+    __builtin_amdgcn_sched_barrier(0);  // keep e0's loads ahead of e1's (in-order waits)
+    load_entries(s0 + U, e1);
+    resolve_values(e0);
+    for (uint64_t p = s0; p < s1; p += 3 * U) {
+        step(e0, e1, e2, p);
+        if (p + U >= s1) break;
+        step(e1, e2, e0, p + U);
+        if (p + 2 * U >= s1) break;
+        step(e2, e0, e1, p + 2 * U);
     }
 
     // ---- join the runs' edge rows across the G groups of the wave ----
@@ -368,9 +406,11 @@ hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, hipStream_t st)
 {
     const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
     if (fused)
-        mttkrp_seg_kernel<FT, VEC, L, STRIDED, true><<<grid, 256, 0, st>>>(args);
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, true, false><<<grid, 256, 0, st>>>(args);
+    else if (args.perm)
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, true><<<grid, 256, 0, st>>>(args);
     else
-        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false><<<grid, 256, 0, st>>>(args);
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, false><<<grid, 256, 0, st>>>(args);
     return hipGetLastError();
 }
 

@@ -211,11 +211,13 @@ hipError_t launch_radix_hist(const uint32_t *keys, uint64_t n, int shift, uint32
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in,
-                                                            const uint32_t *__restrict__ perm_in, uint64_t n,
+// The scatter moves the key and every payload array (the permutation, the
+// other modes' indices and the values) together, so the last pass writes the
+// sorted SoA copy directly and nothing is gathered afterwards.
+__global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in, uint64_t n,
                                                             int shift, const uint32_t *__restrict__ offsets,
                                                             uint32_t ntiles, uint32_t *__restrict__ keys_out,
-                                                            uint32_t *__restrict__ perm_out)
+                                                            SortPayload pl)
 {
     __shared__ uint32_t next[kRadix];           // next free output slot of each digit
     __shared__ uint32_t wcnt[4][kRadix + 1];    // this round's count per wave (+1: idle lanes)
@@ -245,7 +247,8 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
             uint32_t pos = next[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
             keys_out[pos] = key;
-            perm_out[pos] = perm_in ? perm_in[idx] : (uint32_t)idx;
+            pl.out[0][pos] = pl.in[0] ? pl.in[0][idx] : (uint32_t)idx;  // permutation
+            for (int k = 1; k < pl.count; ++k) pl.out[k][pos] = pl.in[k][idx];
         }
         __syncthreads();
         for (uint32_t dd = threadIdx.x; dd < kRadix; dd += 256) {
@@ -256,12 +259,10 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
     }
 }
 
-hipError_t launch_radix_scatter(const uint32_t *keys_in, const uint32_t *perm_in, uint64_t n, int shift,
-                                const uint32_t *offsets, uint32_t ntiles, uint32_t *keys_out, uint32_t *perm_out,
-                                hipStream_t st)
+hipError_t launch_radix_scatter(const uint32_t *keys_in, uint64_t n, int shift, const uint32_t *offsets,
+                                uint32_t ntiles, uint32_t *keys_out, const SortPayload &pl, hipStream_t st)
 {
-    radix_scatter_kernel<<<ntiles, kSortThreads, 0, st>>>(keys_in, perm_in, n, shift, offsets, ntiles, keys_out,
-                                                          perm_out);
+    radix_scatter_kernel<<<ntiles, kSortThreads, 0, st>>>(keys_in, n, shift, offsets, ntiles, keys_out, pl);
     return hipGetLastError();
 }
 
@@ -329,9 +330,13 @@ hipError_t launch_rowptr(const uint32_t *sorted_rows, uint64_t n, uint32_t nrows
 // partial per chunk: the first chunk c_a in its tail slot (2*c_a + 1), every
 // later chunk c in its head slot (2*c). This kernel sums those partials in a
 // fixed order (deterministic), scales by alpha and stores the row; rows with
-// no nonzeros get zeros. Each wave takes 64 rows at a time; lanes flag the
-// rows that need work, then the whole wave reduces one split row at a time.
+// no nonzeros get zeros. Each wave takes 64 rows at a time and ballots the
+// rows that need work: rows with few partials are summed one per lane group
+// (G rows at once), rows with many partials by the whole wave, every group
+// taking a strided share with several loads in flight.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kFixupLight = 16;  // at most this many partials: one lane group per row
+
 template <int VEC, int L, bool STRIDED>
 __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__ rowptr, uint32_t nrows,
                                                     const float *__restrict__ part, uint32_t ldp,
@@ -342,8 +347,10 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
     using S = Slice<float, VEC, STRIDED>;
     const int lane = threadIdx.x & 63;
     const int g = lane / L, j = lane % L;
+    const bool lane_on = S::active(j, rank);
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    auto slot_of = [&](uint64_t ca, uint64_t q) { return q == 0 ? 2 * ca + 1 : 2 * (ca + q); };
     for (uint64_t t = wid; t * 64 < nrows; t += waves) {
         const uint64_t r = t * 64 + lane;
         uint32_t a = 0, b = 0;
@@ -353,26 +360,62 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
         }
         const bool empty = r < nrows && a == b;
         const bool split = r < nrows && a < b && (a / chunk) != ((b - 1) / chunk);
+        const uint64_t cnt = split ? (b - 1) / chunk - a / chunk + 1 : 0;
         if (empty) {  // each lane clears its own row
             float *o = out + r * (uint64_t)ldo;
             for (uint32_t c = 0; c < rank; ++c) o[c] = 0.0f;
         }
-        uint64_t todo = __ballot(split);
-        while (todo) {
-            const int src = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            const uint64_t rr = t * 64 + src;
+        // light rows: lane group g takes the g-th remaining one
+        uint64_t light = __ballot(split && cnt <= kFixupLight);
+        while (light) {
+            uint64_t m = light;
+            for (int i = 0; i < g && m; ++i) m &= m - 1;
+            // The shuffles run with every lane active: a shuffle whose source lane is
+            // inactive yields 0, and the row's lane may sit in a group without a row.
+            const int src = m ? __ffsll((long long)m) - 1 : 0;
             const uint32_t aa = __shfl(a, src), bb = __shfl(b, src);
-            const uint64_t ca = aa / chunk, cb = (bb - 1) / chunk;
-            const uint64_t cnt = cb - ca + 1;
+            if (m && bb > aa) {
+                const uint64_t ca = aa / chunk, n = (bb - 1) / chunk - ca + 1;
+                float acc[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+                if (lane_on) {
+#pragma unroll 4
+                    for (uint64_t q = 0; q < n; ++q) {
+                        float v[VEC];
+                        S::load_f(part + slot_of(ca, q) * ldp, j, rank, v);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] += v[e];
+                    }
+                    store_slice<VEC, STRIDED>(out + (t * 64 + src) * (uint64_t)ldo, j, rank, acc, alpha);
+                }
+            }
+            for (int i = 0; i < G && light; ++i) light &= light - 1;
+        }
+        // heavy rows: the whole wave, G strided shares with 8 loads in flight per lane
+        uint64_t heavy = __ballot(split && cnt > kFixupLight);
+        while (heavy) {
+            const int src = __ffsll((long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const uint32_t aa = __shfl(a, src), bb = __shfl(b, src);
+            const uint64_t ca = aa / chunk, n = (bb - 1) / chunk - ca + 1;
             float acc[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
-            if (S::active(j, rank)) {
-                for (uint64_t q = g; q < cnt; q += G) {
-                    const uint64_t slot = q == 0 ? 2 * ca + 1 : 2 * (ca + q);
+            if (lane_on) {
+                uint64_t q = g;
+                for (; q + 7 * G < n; q += 8 * G) {
+                    float v[8][VEC];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) S::load_f(part + slot_of(ca, q + u * G) * ldp, j, rank, v[u]);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] += v[u][e];
+                }
+                for (; q < n; q += G) {
                     float v[VEC];
-                    S::load_f(part + slot * ldp, j, rank, v);
+                    S::load_f(part + slot_of(ca, q) * ldp, j, rank, v);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc[e] += v[e];
                 }
@@ -381,7 +424,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
             for (int off = L; off < 64; off <<= 1)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], off);
-            if (g == 0 && S::active(j, rank)) store_slice<VEC, STRIDED>(out + rr * ldo, j, rank, acc, alpha);
+            if (g == 0 && lane_on) store_slice<VEC, STRIDED>(out + (t * 64 + src) * (uint64_t)ldo, j, rank, acc, alpha);
         }
     }
 }

@@ -282,6 +282,26 @@ def make_coo(spec: TensorSpec, threads: int = 8) -> CooTensor:
     return CooTensor(dims, np.ascontiguousarray(inds, dtype=np.uint32), vals, spec)
 
 
+GENERATOR_VERSION = 1
+
+
+def load_or_make_coo(spec: TensorSpec, cache_dir: Optional[str] = None) -> CooTensor:
+    """make_coo with an optional on-disk cache keyed by the spec and generator version."""
+    if not cache_dir:
+        return make_coo(spec)
+    import hashlib
+    import os
+    key = hashlib.sha256(repr((spec, GENERATOR_VERSION)).encode()).hexdigest()[:20]
+    base = os.path.join(cache_dir, f"coo_{key}")
+    if os.path.exists(base + "_vals.npy"):
+        return CooTensor(tuple(spec.dims), np.load(base + "_inds.npy"), np.load(base + "_vals.npy"), spec)
+    coo = make_coo(spec)
+    os.makedirs(cache_dir, exist_ok=True)
+    np.save(base + "_inds.npy", coo.inds)
+    np.save(base + "_vals.npy", coo.vals)
+    return coo
+
+
 def make_factors(spec: TensorSpec, rank: Optional[int] = None, scale: float = 1.0):
     """N(0, scale^2) float32 factor matrices, row-major I_k x R."""
     R = spec.rank if rank is None else int(rank)

@@ -34,8 +34,12 @@ def test_status_strings_and_host_argument_checks():
     n = ctypes.c_size_t()
     dims = (ctypes.c_uint64 * 3)(100, 80, 60)
     assert lib.pasta_coo_workspace_bytes(3, dims, 20000, ctypes.byref(n)) == 0
-    # 3 modes x (3 index copies + values + perm) + rowptrs + sort scratch
-    assert n.value >= 3 * 5 * 20000 * 4 + 4 * 20000 * 4
+    # 3 modes x (3 index copies + values + perm); every mode sorts in one 8-bit pass
+    assert 3 * 5 * 20000 * 4 <= n.value < 3 * 5 * 20000 * 4 + 300_000
+    big = (ctypes.c_uint64 * 3)(1000, 80, 60)
+    assert lib.pasta_coo_workspace_bytes(3, big, 20000, ctypes.byref(n)) == 0
+    # two ping-pong sets of (key, permutation, 2 indices, values) for multi-pass sorts
+    assert n.value >= 3 * 5 * 20000 * 4 + 2 * 5 * 20000 * 4
     assert lib.pasta_coo_workspace_bytes(1, dims, 10, ctypes.byref(n)) == 3  # order 1 unsupported
     assert lib.pasta_coo_workspace_bytes(9, dims, 10, ctypes.byref(n)) == 3
     assert lib.pasta_coo_workspace_bytes(3, None, 10, ctypes.byref(n)) == 1

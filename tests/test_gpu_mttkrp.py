@@ -150,7 +150,8 @@ def _layout(rows_per_nnz, dims, seed):
 
 
 @pytest.mark.parametrize("case", ["one_row", "every_nnz_own_row", "chunk_aligned", "chunk_plus_one",
-                                  "chunk_minus_one", "sub_run_edges", "tail_only", "single_nnz", "empty_rows"])
+                                  "chunk_minus_one", "sub_run_edges", "tail_only", "single_nnz", "empty_rows",
+                                  "lone_split_row_high_lane"])
 @pytest.mark.parametrize("R", [32, 64, 100])
 def test_adversarial_layouts(case, R):
     """Row layouts that stress the chunk and lane-group edges (mode 0 carries the layout)."""
@@ -177,6 +178,11 @@ def test_adversarial_layouts(case, R):
     elif case == "tail_only":
         rows = np.sort(rng.integers(0, 5, C * 3 + 17))
         dims = (9, 300, 200)
+    elif case == "lone_split_row_high_lane":
+        # rows 0..62 hold one nonzero each, row 63 crosses the first chunk edge: the fixup
+        # sees one light split row, held by the last lane of its 64-row tile
+        rows = np.concatenate([np.arange(63), np.full(C + 10, 63), np.arange(64, 200)])
+        dims = (200, 300, 200)
     elif case == "single_nnz":
         rows = np.array([3])
         dims = (6, 5, 4)
