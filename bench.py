@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config", type=int, default=2, help="2 (headline), 3 or 5: MTTKRP workload")
     ap.add_argument("--mttkrp-only", action="store_true", help="time only the all-mode MTTKRP (profiling runs)")
+    ap.add_argument("--factor-dtype", choices=["f32", "bf16"], default="f32",
+                    help="factor storage of the MTTKRP step (arithmetic is fp32 either way)")
     ap.add_argument("--cache", default=os.environ.get("PASTA_BENCH_CACHE", ""),
                     help="directory for cached generated tensors (reused between runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -199,10 +201,13 @@ def main():
     inds_d = torch.from_numpy(coo.inds.view(np.int32)).to(dev)
     vals_d = torch.from_numpy(coo.vals).to(dev)
     Ud = [torch.from_numpy(u).to(dev) for u in U]
+    if args.factor_dtype == "bf16":
+        Ud = [api.cast_bf16(u) for u in Ud]
     outs = [torch.empty((d, R), dtype=torch.float32, device=dev) for d in coo.dims]
     ws_coo = torch.empty(api.coo_workspace_bytes(coo.dims, coo.nnz), dtype=torch.uint8, device=dev)
     X = api.Coo(coo.dims, inds_d, vals_d, workspace=ws_coo)
-    ws_m = torch.empty(max(api.mttkrp_workspace_bytes(X, n, R) for n in range(N)), dtype=torch.uint8, device=dev)
+    ws_m = torch.empty(max(api.mttkrp_workspace_bytes(X, n, R, Ud[0].dtype) for n in range(N)), dtype=torch.uint8,
+                       device=dev)
 
     do_cp = not args.mttkrp_only and args.config == 2
     if do_cp:
@@ -294,7 +299,7 @@ def main():
     M = coo.nnz
     t_modes = sum(sum(c) for c in call) / len(recs)  # ms per all-mode MTTKRP
     value = N * M / (t_modes * 1e-3) / 1e9
-    sf = 4
+    sf = 2 if args.factor_dtype == "bf16" else 4
     kern_ms = [sum(k) / len(k) for k in kern]
     alg_bytes = [bytes_alg(N, R, sf, M, coo.dims[n]) for n in range(N)]
     achieved = sum(alg_bytes) / (sum(kern_ms) * 1e-3) / 1e9  # GB/s over the launches of all modes
@@ -318,7 +323,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": spec.name, "dims": list(coo.dims), "nnz": M, "rank": R, "order": N,
-                   "factor_dtype": "f32", "distribution": f"Zipf{spec.zipf} over seeded permutations, distinct",
+                   "factor_dtype": args.factor_dtype, "distribution": f"Zipf{spec.zipf} over seeded permutations, distinct",
                    "values": spec.values, "seed": spec.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,

@@ -12,8 +12,9 @@ Section 5.2 Alg. 6 of the suite):
   * ``cp_sample``: mhat_m = sum_r prod_k U_k[i_k(m), r];
   * ``cp_loss``: 1/2 sum_m (mhat_m - x_m)^2 and its residuals;
   * ``cp_grad``: d loss / d U_n = MTTKRP_n with the residuals as values;
-  * ``sort_perm`` / ``rowptr``: the stable mode-n order of the nonzeros and
-    the row offsets of the sorted stream (a library sort as the step);
+  * ``sort_perm`` / ``mode_orders`` / ``rowptr``: stable orders of the
+    nonzeros by one mode, the chained per-mode orders, and the row offsets of
+    a sorted stream (a library sort as the step);
   * ``bf16_round``: float32 -> bfloat16, round to nearest, ties to even.
 """
 from __future__ import annotations
@@ -162,6 +163,22 @@ def cp_grad(dims, inds, vals, factors, strategy: str = "seq"):
 def sort_perm(rows) -> np.ndarray:
     """Stable order of the nonzeros by their mode-n index (ties keep caller order)."""
     return np.argsort(np.asarray(rows), kind="stable").astype(np.uint32)
+
+
+def mode_orders(inds):
+    """The order of the nonzeros for every mode: mode n's order is the stable sort
+    by i_n of mode n-1's order, starting from mode N-1 sorted stably out of the
+    caller's order. Equivalently, mode n's order is lexicographic in
+    (i_n, i_{n-1}, ..., i_0), then i_{N-1} (for n < N-1), then caller position."""
+    inds = np.asarray(inds)
+    N = inds.shape[0]
+    prev = np.argsort(inds[N - 1], kind="stable")
+    out = []
+    for n in range(N):
+        o = prev[np.argsort(inds[n][prev], kind="stable")]
+        out.append(o.astype(np.uint32))
+        prev = o
+    return out
 
 
 def rowptr(sorted_rows, size: int) -> np.ndarray:

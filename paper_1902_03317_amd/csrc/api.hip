@@ -366,49 +366,69 @@ pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz
     uint32_t *hist = at(L.hist);
     uint32_t *scanpart = at(L.scanpart);
     const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
-    for (uint32_t n = 0; n < order; ++n) {
-        auto &md = X->mode[n];
-        if (nnz > 0) {
-            const int bits = key_bits(dims[n]);
-            const int passes = (bits + kRadixBits - 1) / kRadixBits;
-            if (passes == 0) {  // a mode of size 1: the order is the caller's
-                HIPCHK_X(launch_identity_sort(d_inds[n], nnz, md.sinds[n], md.perm, st));
-                HIPCHK_X(launch_permute(order, n, nnz, md.perm, d_inds, d_vals, md.sinds, md.svals, st));
-            } else {
-                // inputs of the first pass: the caller's arrays, identity permutation
-                const uint32_t *kin = d_inds[n];
-                SortPayload pl{};
+    // Mode orders, chained: mode n's order is the stable sort by i_n of mode
+    // n-1's order, so within a row of mode n the nonzeros are ordered by i_{n-1}
+    // (then i_{n-2}, ...). The chain starts from mode N-1 sorted out of the
+    // caller's order (written into mode N-1's buffers, which its own final sort
+    // later overwrites): N + 1 stable sorts in all.
+    if (nnz > 0) {
+        for (uint32_t stage = 0; stage <= order; ++stage) {
+            const uint32_t n = stage == 0 ? order - 1 : stage - 1;
+            auto &md = X->mode[n];
+            const uint32_t *src_key;
+            SortPayload pl{};
+            int cnt = 1;
+            if (stage == 0) {  // from the caller's arrays, identity permutation
+                src_key = d_inds[n];
                 pl.in[0] = nullptr;
-                int cnt = 1;
                 for (uint32_t k = 0; k < order; ++k)
                     if (k != n) pl.in[cnt++] = d_inds[k];
                 pl.in[cnt++] = reinterpret_cast<const uint32_t *>(d_vals);
-                pl.count = cnt;
-                for (int ps = 0; ps < passes; ++ps) {
-                    const bool last = ps == passes - 1;
-                    uint32_t *kout;
-                    if (last) {
-                        kout = md.sinds[n];
-                        int c = 1;
-                        pl.out[0] = md.perm;
-                        for (uint32_t k = 0; k < order; ++k)
-                            if (k != n) pl.out[c++] = md.sinds[k];
-                        pl.out[c++] = reinterpret_cast<uint32_t *>(md.svals);
-                    } else {
-                        const int set = ps & 1;
-                        kout = at(L.tmp[set][0]);
-                        for (int c = 0; c < cnt; ++c) pl.out[c] = at(L.tmp[set][c + 1]);
-                    }
-                    HIPCHK_X(launch_radix_hist(kin, nnz, ps * kRadixBits, hist, L.ntiles, st));
-                    HIPCHK_X(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
-                    HIPCHK_X(launch_radix_scatter(kin, nnz, ps * kRadixBits, hist, L.ntiles, kout, pl, st));
-                    kin = kout;
-                    for (int c = 0; c < cnt; ++c) pl.in[c] = pl.out[c];
+            } else {  // from the previous mode's sorted copy; permutations compose
+                const auto &pm = X->mode[(n + order - 1) % order];
+                src_key = pm.sinds[n];
+                pl.in[0] = pm.perm;
+                for (uint32_t k = 0; k < order; ++k)
+                    if (k != n) pl.in[cnt++] = pm.sinds[k];
+                pl.in[cnt++] = reinterpret_cast<const uint32_t *>(pm.svals);
+            }
+            pl.count = cnt;
+            auto set_final = [&]() {
+                int c = 1;
+                pl.out[0] = md.perm;
+                for (uint32_t k = 0; k < order; ++k)
+                    if (k != n) pl.out[c++] = md.sinds[k];
+                pl.out[c++] = reinterpret_cast<uint32_t *>(md.svals);
+            };
+            const int bits = key_bits(dims[n]);
+            const int passes = (bits + kRadixBits - 1) / kRadixBits;
+            if (passes == 0) {  // a mode of size 1: the order is unchanged
+                set_final();
+                HIPCHK_X(launch_copy_payload(src_key, nnz, md.sinds[n], pl, st));
+                continue;
+            }
+            const uint32_t *kin = src_key;
+            for (int ps = 0; ps < passes; ++ps) {
+                const bool last = ps == passes - 1;
+                uint32_t *kout;
+                if (last) {
+                    kout = md.sinds[n];
+                    set_final();
+                } else {
+                    const int set = ps & 1;
+                    kout = at(L.tmp[set][0]);
+                    for (int c = 0; c < cnt; ++c) pl.out[c] = at(L.tmp[set][c + 1]);
                 }
+                HIPCHK_X(launch_radix_hist(kin, nnz, ps * kRadixBits, hist, L.ntiles, st));
+                HIPCHK_X(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
+                HIPCHK_X(launch_radix_scatter(kin, nnz, ps * kRadixBits, hist, L.ntiles, kout, pl, st));
+                kin = kout;
+                for (int c = 0; c < cnt; ++c) pl.in[c] = pl.out[c];
             }
         }
-        HIPCHK_X(launch_rowptr(md.sinds[n], nnz, (uint32_t)dims[n], md.rowptr, st));
     }
+    for (uint32_t n = 0; n < order; ++n)
+        HIPCHK_X(launch_rowptr(X->mode[n].sinds[n], nnz, (uint32_t)dims[n], X->mode[n].rowptr, st));
     uint32_t host_flag = 0;
     HIPCHK_X(hipMemcpyAsync(&host_flag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIPCHK_X(hipStreamSynchronize(st));

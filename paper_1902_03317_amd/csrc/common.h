@@ -213,6 +213,8 @@ struct SortPayload {
 };
 hipError_t launch_radix_scatter(const uint32_t *keys_in, uint64_t n, int shift, const uint32_t *offsets,
                                 uint32_t ntiles, uint32_t *keys_out, const SortPayload &pl, hipStream_t st);
+hipError_t launch_copy_payload(const uint32_t *keys_in, uint64_t n, uint32_t *keys_out, const SortPayload &pl,
+                               hipStream_t st);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *partials,
                                  hipStream_t st);
 uint64_t scan_partials_count(uint64_t n);

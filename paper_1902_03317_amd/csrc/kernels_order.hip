@@ -51,17 +51,59 @@ struct MttkrpArgs {
     float alpha;
 };
 
+// The index/value stream is read once: non-temporal loads keep it from
+// displacing factor rows in L2.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p)
+{
+#ifdef PASTA_TEMPORAL_STREAM
+    return *p;
+#else
+    return __builtin_nontemporal_load(p);
+#endif
+}
+
+#ifdef PASTA_WAVES_PER_EU
+#define PASTA_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PASTA_WAVES_PER_EU)))
+#else
+#define PASTA_OCCUPANCY
+#endif
+
+// Chunk handled by a wave. Workgroups are dealt round-robin to the 8 XCDs
+// (workgroup b runs on XCD b % 8); renumbering them so that each XCD takes one
+// contiguous run of chunks keeps the factor rows a run touches in that XCD's
+// own L2.
+__device__ __forceinline__ uint32_t chunk_of_wave(uint32_t nblocks)
+{
+#ifdef PASTA_NO_XCD_REMAP
+    return blockIdx.x * 4 + (threadIdx.x >> 6);
+#else
+    const uint32_t b = blockIdx.x, x = b % 8, i = b / 8;
+    const uint32_t q = nblocks / 8, r = nblocks % 8;
+    const uint32_t logical = x * q + (x < r ? x : r) + i;
+    return logical * 4 + (threadIdx.x >> 6);
+#endif
+}
+
 template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR>
-__global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
+__global__ __launch_bounds__(256) PASTA_OCCUPANCY void mttkrp_seg_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;
     constexpr int U = kStep;
     constexpr int EPL = L >= U ? 1 : U / L;  // entries each lane loads per step
     using S = Slice<FT, VEC, STRIDED>;
     using Packed = typename S::Packed;
+    // Row reuse pays with bf16 factors (measured: ~8% faster per mode on the
+    // 50M-nonzero Zipf tensor) but costs ~20% with fp32 rows, so it is only
+    // compiled in for bf16.
+#ifdef PASTA_REUSE
+    constexpr bool kReuse = PASTA_REUSE != 0;
+#else
+    constexpr bool kReuse = sizeof(FT) == 2;
+#endif
 
     const int lane = threadIdx.x & 63;
-    const uint32_t chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t chunk = chunk_of_wave(gridDim.x);
     if (chunk >= a.nchunks) return;  // whole wave leaves together
     const int g = lane / L, j = lane % L;
     const int gbase = lane & ~(L - 1);
@@ -79,6 +121,16 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) rowfac[e] = 0.0f;
     double loss = 0.0;
+    // the factor rows of the previous nonzero (their indices in lastk), reused
+    // without a memory request when the next nonzero names the same rows
+    float rowk[NM1][VEC];
+    uint32_t lastk[NM1];
+#pragma unroll
+    for (int k = 0; k < NM1; ++k) {
+        lastk[k] = kNoRow;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) rowk[k][e] = 0.0f;
+    }
     uint32_t cur = kNoRow, hrow = kNoRow;
     bool multi = false;  // this group has already closed its first row
 
@@ -100,13 +152,13 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
         for (int t = 0; t < EPL; ++t) {
             const uint64_t q0 = p + (uint64_t)(j + L * t);
             const uint64_t q = q0 < last ? q0 : last;
-            E.r[t] = a.row[q];
+            E.r[t] = stream_load(a.row + q);
 #pragma unroll
-            for (int k = 0; k < NM1; ++k) E.i[t][k] = a.idx[k][q];
+            for (int k = 0; k < NM1; ++k) E.i[t][k] = stream_load(a.idx[k] + q);
             if constexpr (OVR)
-                E.v[t] = __uint_as_float(a.perm[q]);
+                E.v[t] = __uint_as_float(stream_load(a.perm + q));
             else
-                E.v[t] = a.vals[q];
+                E.v[t] = stream_load(a.vals + q);
         }
     };
     auto resolve_values = [&](Entries &E) {
@@ -125,6 +177,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
         uint32_t ru[U];
         float vu[U];
         Packed gp[U][NM1];
+        bool reuse[U][NM1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int src = gbase | (u % L);
@@ -133,12 +186,11 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 #pragma unroll
             for (int k = 0; k < NM1; ++k) {
                 const uint32_t iu = (uint32_t)__shfl((int)E0.i[u / L][k], src);
-                if ((uint32_t)u < navail && lane_on) {
+                // the same factor row as the previous nonzero: keep it, no request
+                reuse[u][k] = kReuse && iu == lastk[k];
+                if ((uint32_t)u < navail) lastk[k] = iu;
+                if ((uint32_t)u < navail && lane_on && !reuse[u][k])
                     S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, j, a.rank, gp[u][k]);
-                } else {
-#pragma unroll
-                    for (int w = 0; w < S::kWords; ++w) gp[u][k].w[w] = 0u;
-                }
             }
         }
         __builtin_amdgcn_sched_barrier(0);  // the prefetch goes out after this step's gathers
@@ -147,15 +199,16 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if ((uint32_t)u >= navail) break;
+#pragma unroll
+            for (int k = 0; k < NM1; ++k)
+                if (!reuse[u][k]) S::unpack(gp[u][k], rowk[k]);
             float q[VEC];
-            S::unpack(gp[u][0], q);
 #pragma unroll
-            for (int k = 1; k < NM1; ++k) {
-                float t[VEC];
-                S::unpack(gp[u][k], t);
+            for (int e = 0; e < VEC; ++e) q[e] = rowk[0][e];
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) q[e] *= t[e];
-            }
+            for (int k = 1; k < NM1; ++k)
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) q[e] *= rowk[k][e];
             if (ru[u] != cur) {
                 if (cur != kNoRow) {
                     if (!multi) {  // the run's first row may continue in earlier runs: keep it
@@ -179,7 +232,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                 float d = 0.0f;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) d += rowfac[e] * q[e];
-                d = group_sum<L>(d);
+                d = group_sum<L>(lane_on ? d : 0.0f);
                 w = d - vu[u];
                 if (j == 0) loss += 0.5 * (double)w * (double)w;
             }

@@ -213,24 +213,49 @@ hipError_t launch_radix_hist(const uint32_t *keys, uint64_t n, int shift, uint32
 
 // The scatter moves the key and every payload array (the permutation, the
 // other modes' indices and the values) together, so the last pass writes the
-// sorted SoA copy directly and nothing is gathered afterwards.
+// sorted SoA copy directly and nothing is gathered afterwards. Writes are
+// staged in LDS: each key's place inside the tile (digit start within the
+// tile + equal digits before it) is found first, the tile is laid out in LDS
+// in that order, and then each digit's run is written to its global place as
+// one contiguous range, so global writes are coalesced. Payload arrays go
+// through LDS one at a time.
 __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in, uint64_t n,
                                                             int shift, const uint32_t *__restrict__ offsets,
                                                             uint32_t ntiles, uint32_t *__restrict__ keys_out,
                                                             SortPayload pl)
 {
-    __shared__ uint32_t next[kRadix];           // next free output slot of each digit
+    __shared__ uint32_t lstart[kRadix];         // first slot of each digit inside the tile
+    __shared__ uint32_t gstart[kRadix];         // its first place in the output
+    __shared__ uint32_t next[kRadix];           // next free slot of each digit inside the tile
     __shared__ uint32_t wcnt[4][kRadix + 1];    // this round's count per wave (+1: idle lanes)
+    __shared__ uint32_t s_key[kSortTile];
+    __shared__ uint32_t s_val[kSortTile];
+    __shared__ uint32_t lds4[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (uint32_t d = threadIdx.x; d < kRadix; d += 256) next[d] = offsets[(uint64_t)d * ntiles + blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t tile_n = (uint32_t)(n - base < kSortTile ? n - base : kSortTile);
+    // this tile's digit counts from the scanned histogram (digit-major, exclusive)
+    {
+        const uint32_t d = threadIdx.x;
+        const uint64_t j = (uint64_t)d * ntiles + blockIdx.x;
+        const uint64_t last = (uint64_t)kRadix * ntiles - 1;
+        const uint32_t g0 = offsets[j];
+        const uint32_t cnt = (j < last ? offsets[j + 1] : (uint32_t)n) - g0;
+        gstart[d] = g0;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan_u32(cnt, lds4, &total);
+        lstart[d] = ex;
+        next[d] = ex;
+    }
     for (uint32_t d = threadIdx.x; d < 4 * (kRadix + 1); d += 256) (&wcnt[0][0])[d] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t lpos[kSortItems];
+#pragma unroll
     for (uint32_t round = 0; round < kSortItems; ++round) {
-        const uint64_t idx = base + (uint64_t)round * kSortThreads + threadIdx.x;
-        const bool on = idx < n;
-        const uint32_t key = on ? keys_in[idx] : 0u;
+        const uint32_t li = round * kSortThreads + threadIdx.x;
+        const bool on = li < tile_n;
+        const uint32_t key = on ? keys_in[base + li] : 0u;
         const uint32_t d = on ? ((key >> shift) & (kRadix - 1)) : kRadix;
         // lanes of this wave holding the same digit (idle lanes share digit kRadix)
         uint64_t peers = ~0ull;
@@ -243,17 +268,38 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
         const uint32_t rank = __popcll(peers & lt_mask);
         if (rank == 0) wcnt[wave][d] = __popcll(peers);
         __syncthreads();
+        lpos[round] = 0;
         if (on) {
             uint32_t pos = next[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            keys_out[pos] = key;
-            pl.out[0][pos] = pl.in[0] ? pl.in[0][idx] : (uint32_t)idx;  // permutation
-            for (int k = 1; k < pl.count; ++k) pl.out[k][pos] = pl.in[k][idx];
+            lpos[round] = pos;
+            s_key[pos] = key;
         }
         __syncthreads();
         for (uint32_t dd = threadIdx.x; dd < kRadix; dd += 256) {
             next[dd] += wcnt[0][dd] + wcnt[1][dd] + wcnt[2][dd] + wcnt[3][dd];
             wcnt[0][dd] = wcnt[1][dd] = wcnt[2][dd] = wcnt[3][dd] = 0;
+        }
+        __syncthreads();
+    }
+    // keys, in tile order: slot i of digit d goes to gstart[d] + (i - lstart[d])
+    for (uint32_t i = threadIdx.x; i < tile_n; i += kSortThreads) {
+        const uint32_t key = s_key[i];
+        const uint32_t d = (key >> shift) & (kRadix - 1);
+        keys_out[gstart[d] + (i - lstart[d])] = key;
+    }
+    for (int k = 0; k < pl.count; ++k) {
+        const uint32_t *src = pl.in[k];
+#pragma unroll
+        for (uint32_t round = 0; round < kSortItems; ++round) {
+            const uint32_t li = round * kSortThreads + threadIdx.x;
+            if (li < tile_n) s_val[lpos[round]] = src ? src[base + li] : (uint32_t)(base + li);
+        }
+        __syncthreads();
+        uint32_t *dst = pl.out[k];
+        for (uint32_t i = threadIdx.x; i < tile_n; i += kSortThreads) {
+            const uint32_t d = (s_key[i] >> shift) & (kRadix - 1);
+            dst[gstart[d] + (i - lstart[d])] = s_val[i];
         }
         __syncthreads();
     }
@@ -263,6 +309,25 @@ hipError_t launch_radix_scatter(const uint32_t *keys_in, uint64_t n, int shift, 
                                 uint32_t ntiles, uint32_t *keys_out, const SortPayload &pl, hipStream_t st)
 {
     radix_scatter_kernel<<<ntiles, kSortThreads, 0, st>>>(keys_in, n, shift, offsets, ntiles, keys_out, pl);
+    return hipGetLastError();
+}
+
+// Copy a key array and its payload unchanged (the stable order of a mode of size 1).
+__global__ void copy_payload_kernel(const uint32_t *__restrict__ keys_in, uint64_t n, uint32_t *__restrict__ keys_out,
+                                    SortPayload pl)
+{
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
+        keys_out[p] = keys_in[p];
+        pl.out[0][p] = pl.in[0] ? pl.in[0][p] : (uint32_t)p;
+        for (int k = 1; k < pl.count; ++k) pl.out[k][p] = pl.in[k][p];
+    }
+}
+
+hipError_t launch_copy_payload(const uint32_t *keys_in, uint64_t n, uint32_t *keys_out, const SortPayload &pl,
+                               hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    copy_payload_kernel<<<grid_for(n, 256), 256, 0, st>>>(keys_in, n, keys_out, pl);
     return hipGetLastError();
 }
 

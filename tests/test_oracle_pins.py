@@ -254,6 +254,20 @@ def test_sort_perm_and_rowptr(oracle_lib):
     assert list(rp) == [sum(counts[:i]) for i in range(13)]
 
 
+def test_mode_orders_are_cyclic_lexicographic(oracle_lib):
+    """The chained per-mode orders equal a lexicographic sort on (i_n, i_{n-1}, ..., i_0),
+    then i_{N-1} (for n < N-1), then caller position, checked with Python's own sort."""
+    rng = np.random.default_rng(22)
+    for dims in [(4, 3), (5, 4, 3), (3, 4, 2, 3)]:
+        N = len(dims)
+        inds, _ = rand_coo(rng, dims, 90, dup=True)
+        orders = oracle.mode_orders(inds)
+        for n in range(N):
+            cyc = list(range(n, -1, -1)) + ([N - 1] if n < N - 1 else [])
+            want = sorted(range(90), key=lambda m: tuple(int(inds[k, m]) for k in cyc) + (m,))
+            assert list(orders[n]) == want
+
+
 def test_golden_lexicographic_order(oracle_lib):
     """Section 5.2 example (2,1,1) > (1,1,2) > (1,1,1): composing stable single-mode
     sorts from the last mode to the first yields that lexicographic order."""
