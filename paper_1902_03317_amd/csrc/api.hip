@@ -199,6 +199,7 @@ struct MttkrpPlan {
     KernelShape shape;
     uint32_t sub, nchunks, ldp;
     uint64_t chunk;
+    size_t blk_offset;  // level-one fixup sums follow the chunk partials
     size_t part_bytes;
 };
 
@@ -212,7 +213,9 @@ bool plan_mttkrp(const pasta_coo *X, uint32_t rank, KernelShape s, MttkrpPlan &p
     if (nch > 0x7FFFFFFFull) return false;
     p.nchunks = (uint32_t)nch;
     p.ldp = s.strided ? rank : (rank + 3u) / 4u * 4u;
-    p.part_bytes = align_up((size_t)2 * p.nchunks * p.ldp * sizeof(float));
+    p.blk_offset = align_up((size_t)2 * p.nchunks * p.ldp * sizeof(float));
+    const size_t nblk = (p.nchunks + 63) / 64;
+    p.part_bytes = p.blk_offset + align_up(nblk * p.ldp * sizeof(float));
     return true;
 }
 
@@ -292,7 +295,9 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
         HIPCHK(launch_mttkrp(X->order, l, dt == PASTA_BF16, s, fused, st));
         if (e1) HIPCHK(hipEventRecord(e1, st));
     }
-    HIPCHK(launch_fixup(md.rowptr, (uint32_t)X->dims[mode], l.part, p.ldp, out, ldo, rank, p.chunk, alpha, s, st));
+    float *blk = reinterpret_cast<float *>(static_cast<char *>(work) + p.blk_offset);
+    HIPCHK(launch_fixup(md.rowptr, md.sinds[mode], X->nnz, (uint32_t)X->dims[mode], l.part, p.ldp, blk, p.nchunks, out,
+                        ldo, rank, p.chunk, alpha, s, st));
     return PASTA_OK;
 }
 

@@ -401,12 +401,52 @@ hipError_t launch_rowptr(const uint32_t *sorted_rows, uint64_t n, uint32_t nrows
 // taking a strided share with several loads in flight.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFixupLight = 16;  // at most this many partials: one lane group per row
+constexpr uint32_t kFixupBlock = 64;  // chunks per level-one block
+
+// Level-one sums for rows that span very many chunks. A block of kFixupBlock
+// consecutive chunks whose nonzeros all belong to the row that also holds the
+// nonzero just before the block (two reads decide it, since the stream is
+// sorted) has that row's whole-chunk partials in its head slots; their sum, in
+// a fixed order, goes to blk[b]. The fixup then reads one value per such block
+// instead of kFixupBlock.
+template <int VEC, int L, bool STRIDED>
+__global__ __launch_bounds__(256) void fixup_blocks_kernel(const uint32_t *__restrict__ row, uint64_t nnz,
+                                                           const float *__restrict__ part, uint32_t ldp,
+                                                           float *__restrict__ blk, uint64_t nblk, uint32_t rank,
+                                                           uint64_t chunk)
+{
+    constexpr int G = kWave / L;
+    using S = Slice<float, VEC, STRIDED>;
+    const int lane = threadIdx.x & 63;
+    const int g = lane / L, j = lane % L;
+    const uint64_t b = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (b >= nblk) return;
+    const uint64_t lo = b * kFixupBlock * chunk, hi = (b + 1) * kFixupBlock * chunk;
+    if (lo == 0 || hi > nnz || row[lo - 1] != row[hi - 1]) return;  // not inside one row
+    float acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+    if (S::active(j, rank)) {
+#pragma unroll 8
+        for (uint32_t q = g; q < kFixupBlock; q += G) {
+            float v[VEC];
+            S::load_f(part + 2 * (b * kFixupBlock + q) * ldp, j, rank, v);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[e] += v[e];
+        }
+    }
+#pragma unroll
+    for (int off = L; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], off);
+    if (g == 0 && S::active(j, rank)) store_slice<VEC, STRIDED>(blk + b * ldp, j, rank, acc, 1.0f);
+}
 
 template <int VEC, int L, bool STRIDED>
 __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__ rowptr, uint32_t nrows,
                                                     const float *__restrict__ part, uint32_t ldp,
-                                                    float *__restrict__ out, uint32_t ldo, uint32_t rank,
-                                                    uint64_t chunk, float alpha)
+                                                    const float *__restrict__ blk, float *__restrict__ out,
+                                                    uint32_t ldo, uint32_t rank, uint64_t chunk, float alpha)
 {
     constexpr int G = kWave / L;
     using S = Slice<float, VEC, STRIDED>;
@@ -463,7 +503,23 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
             const int src = __ffsll((long long)heavy) - 1;
             heavy &= heavy - 1;
             const uint32_t aa = __shfl(a, src), bb = __shfl(b, src);
-            const uint64_t ca = aa / chunk, n = (bb - 1) / chunk - ca + 1;
+            const uint64_t ca = aa / chunk, cb = (bb - 1) / chunk;
+            // items: the tail of chunk ca, the heads of chunks ca+1..cb, where the
+            // level-one blocks lying wholly in ca+1..cb-1 (chunks of this row only)
+            // stand for their kFixupBlock heads
+            const uint64_t blo = (ca + 1 + kFixupBlock - 1) / kFixupBlock;
+            const uint64_t bhi_end = cb / kFixupBlock;  // one past the last usable block
+            const bool blocks = blo < bhi_end;
+            const uint64_t n1 = blocks ? blo * kFixupBlock - (ca + 1) : cb - ca;
+            const uint64_t nb = blocks ? bhi_end - blo : 0;
+            const uint64_t n3 = blocks ? cb + 1 - bhi_end * kFixupBlock : 0;
+            const uint64_t n = 1 + n1 + nb + n3;
+            auto item = [&](uint64_t q) -> const float * {
+                if (q == 0) return part + (2 * ca + 1) * ldp;
+                if (q <= n1) return part + 2 * (ca + q) * ldp;
+                if (q <= n1 + nb) return blk + (blo + (q - 1 - n1)) * ldp;
+                return part + 2 * (bhi_end * kFixupBlock + (q - 1 - n1 - nb)) * ldp;
+            };
             float acc[VEC];
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
@@ -472,7 +528,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
                 for (; q + 7 * G < n; q += 8 * G) {
                     float v[8][VEC];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) S::load_f(part + slot_of(ca, q + u * G) * ldp, j, rank, v[u]);
+                    for (int u = 0; u < 8; ++u) S::load_f(item(q + u * G), j, rank, v[u]);
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -480,7 +536,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
                 }
                 for (; q < n; q += G) {
                     float v[VEC];
-                    S::load_f(part + slot_of(ca, q) * ldp, j, rank, v);
+                    S::load_f(item(q), j, rank, v);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc[e] += v[e];
                 }
@@ -494,13 +550,20 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
     }
 }
 
-hipError_t launch_fixup(const uint32_t *rowptr, uint32_t nrows, const float *part, uint32_t ldp, float *out,
-                        uint32_t ldo, uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st)
+hipError_t launch_fixup(const uint32_t *rowptr, const uint32_t *row, uint64_t nnz, uint32_t nrows,
+                        const float *part, uint32_t ldp, float *blk, uint64_t nchunks, float *out, uint32_t ldo,
+                        uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st)
 {
     const uint64_t tiles = ((uint64_t)nrows + 63) / 64;
     const unsigned grid = grid_for(tiles, 4, 4096);
+    const uint64_t nblk = (nchunks + kFixupBlock - 1) / kFixupBlock;
+    const unsigned bgrid = (unsigned)((nblk + 3) / 4);
 #define PASTA_FIXUP(V, LL, STR)                                                                                   \
-    fixup_kernel<V, LL, STR><<<grid, 256, 0, st>>>(rowptr, nrows, part, ldp, out, ldo, rank, chunk, alpha)
+    do {                                                                                                         \
+        if (nblk > 0 && nnz > 0)                                                                                 \
+            fixup_blocks_kernel<V, LL, STR><<<bgrid, 256, 0, st>>>(row, nnz, part, ldp, blk, nblk, rank, chunk);  \
+        fixup_kernel<V, LL, STR><<<grid, 256, 0, st>>>(rowptr, nrows, part, ldp, blk, out, ldo, rank, chunk, alpha); \
+    } while (0)
     if (s.strided) {
         PASTA_FIXUP(4, 64, true);
     } else {

@@ -296,9 +296,16 @@ def load_or_make_coo(spec: TensorSpec, cache_dir: Optional[str] = None) -> CooTe
     if os.path.exists(base + "_vals.npy"):
         return CooTensor(tuple(spec.dims), np.load(base + "_inds.npy"), np.load(base + "_vals.npy"), spec)
     coo = make_coo(spec)
-    os.makedirs(cache_dir, exist_ok=True)
-    np.save(base + "_inds.npy", coo.inds)
-    np.save(base + "_vals.npy", coo.vals)
+    try:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.save(base + "_inds.npy", coo.inds)
+        np.save(base + "_vals.npy", coo.vals)
+    except OSError:  # no room for the cache: drop partial files, carry on uncached
+        for suffix in ("_inds.npy", "_vals.npy"):
+            try:
+                os.remove(base + suffix)
+            except OSError:
+                pass
     return coo
 
 

@@ -152,7 +152,7 @@ def _layout(rows_per_nnz, dims, seed):
 
 @pytest.mark.parametrize("case", ["one_row", "every_nnz_own_row", "chunk_aligned", "chunk_plus_one",
                                   "chunk_minus_one", "sub_run_edges", "tail_only", "single_nnz", "empty_rows",
-                                  "lone_split_row_high_lane"])
+                                  "lone_split_row_high_lane", "long_row_mid_chunk"])
 @pytest.mark.parametrize("R", [32, 64, 100])
 def test_adversarial_layouts(case, R):
     """Row layouts that stress the chunk and lane-group edges (mode 0 carries the layout)."""
@@ -184,6 +184,10 @@ def test_adversarial_layouts(case, R):
         # sees one light split row, held by the last lane of its 64-row tile
         rows = np.concatenate([np.arange(63), np.full(C + 10, 63), np.arange(64, 200)])
         dims = (200, 300, 200)
+    elif case == "long_row_mid_chunk":
+        # one row over ~150 chunks (level-one fixup blocks), ending inside a chunk
+        rows = np.concatenate([np.zeros(100, int), np.ones(C * 147 + 123, int), np.full(50, 2)])
+        dims = (3, 300, 200)
     elif case == "single_nnz":
         rows = np.array([3])
         dims = (6, 5, 4)
