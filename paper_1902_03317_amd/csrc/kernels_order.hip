@@ -59,12 +59,6 @@ __device__ __forceinline__ T stream_load(const T *p)
     return *p;
 }
 
-#ifdef PASTA_WAVES_PER_EU
-#define PASTA_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PASTA_WAVES_PER_EU)))
-#else
-#define PASTA_OCCUPANCY
-#endif
-
 // Chunk handled by a wave. Workgroups are dealt round-robin to the 8 XCDs
 // (workgroup b runs on XCD b % 8); renumbering them so that each XCD takes one
 // contiguous run of chunks keeps the factor rows a run touches in that XCD's
@@ -82,10 +76,11 @@ __device__ __forceinline__ uint32_t chunk_of_wave(uint32_t nblocks)
 }
 
 template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR>
-__global__ __launch_bounds__(256) PASTA_OCCUPANCY void mttkrp_seg_kernel(const MttkrpArgs a)
+__global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;
     constexpr int U = kStep;
+    static_assert((U & (U - 1)) == 0, "steps are powers of two");
     constexpr int EPL = L >= U ? 1 : U / L;  // entries each lane loads per step
     using S = Slice<FT, VEC, STRIDED>;
     using Packed = typename S::Packed;
@@ -116,7 +111,7 @@ __global__ __launch_bounds__(256) PASTA_OCCUPANCY void mttkrp_seg_kernel(const M
     float rowfac[VEC];  // fused: U^(n) slice of the current row
 #pragma unroll
     for (int e = 0; e < VEC; ++e) rowfac[e] = 0.0f;
-    double loss = 0.0;
+    float loss_run = 0.0f;  // fused: this run's sum of squared residuals (<= 256 terms)
     // the factor rows of the previous nonzero (their indices in lastk), reused
     // without a memory request when the next nonzero names the same rows
     float rowk[NM1][VEC];
@@ -248,7 +243,7 @@ __global__ __launch_bounds__(256) PASTA_OCCUPANCY void mttkrp_seg_kernel(const M
                 for (int e = 0; e < VEC; ++e) d += rowfac[e] * q[e];
                 d = group_sum<L>(lane_on ? d : 0.0f);
                 w = d - vu[u];
-                if (j == 0) loss += 0.5 * (double)w * (double)w;
+                loss_run += w * w;
             }
 #pragma unroll
             for (int e = 0; e < VEC; ++e) acc[e] += w * q[e];
@@ -319,8 +314,8 @@ __global__ __launch_bounds__(256) PASTA_OCCUPANCY void mttkrp_seg_kernel(const M
     if (cur != kNoRow && !next_cont) emit(cur, carry);
 
     if constexpr (FUSED) {
-        if (a.loss_part) {
-            const double tot = wave_sum_f64(loss);
+        if (a.loss_part) {  // every lane of a group holds its run's sum: count it once per group
+            const double tot = wave_sum_f64(j == 0 ? 0.5 * (double)loss_run : 0.0);
             if (lane == 0) a.loss_part[chunk] = tot;
         }
     }
