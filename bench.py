@@ -345,6 +345,24 @@ def main():
                               "bf16_speedup": round(line["breakdown_ms"]["cp_step_f32"] /
                                                     line["breakdown_ms"]["cp_step_bf16"], 3)}
         line["cp_loss_last"] = {"f32": loss_hist[-1][0], "bf16": loss_hist[-1][1]}
+    if do_cp:
+        # CP-ALS sweep (MTTKRP + normal equations + normalisation, every mode), timed apart
+        Ua = [u.clone() for u in Ud] if args.factor_dtype == "f32" else [torch.from_numpy(u).to(dev) for u in U]
+        lam = torch.empty(R, dtype=torch.float32, device=dev)
+        import ctypes as _ct
+        nb = _ct.c_size_t()
+        plib.pasta_cp_als_workspace_bytes(X.handle, R, _ct.byref(nb))
+        ws_a = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            api.cp_als_sweep(X, Ua, lam=lam, workspace=ws_a)
+        ts = []
+        for _ in range(5):
+            e0, e1 = hip.event(), hip.event()
+            hip.record(e0, s_ptr)
+            _, fit, _ = api.cp_als_sweep(X, Ua, lam=lam, workspace=ws_a)
+            hip.record(e1, s_ptr)
+            ts.append(hip.ms(e0, e1))
+        line["cp_als_sweep_ms"] = round(sorted(ts)[len(ts) // 2], 4)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (m, inds_s, vals_s, outs_o) = cpu_baseline(coo, U)

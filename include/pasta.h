@@ -156,6 +156,25 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
                            uint32_t ldf, float alpha, float *const *d_grads, uint32_t ldg, double *d_loss,
                            void *d_work, size_t work_bytes, void *stream);
 
+/* One sweep of CP-ALS (alternating least squares, one of the CPD methods of
+ * Section 3.1.1, whose bottleneck is the MTTKRP): for every mode n in turn,
+ *   M = MTTKRP_n(X; U),  V = Hadamard_{k != n} (U_k^T U_k),
+ *   U_n <- M V^{-1} (Cholesky of V),  lambda_r = ||U_n[:, r]||_2,
+ *   U_n[:, r] /= lambda_r (zero columns stay zero).
+ *   d_factors  host array of `order` device pointers to fp32 I_k x ldf
+ *              factors, updated in place; rank R <= 64.
+ *   d_lambda   R fp32 column norms of the last mode after the sweep.
+ *   d_fit      (NULL or device scalar) 1 - ||X - [[lambda; U]]|| / ||X||,
+ *              with the norms in fp64 (||X||^2 = sum of squared values, so
+ *              repeated coordinates are taken as separate entries).
+ *   d_info     (NULL or device uint32) set to 1 if some V was not
+ *              numerically positive definite, else 0.
+ * d_work >= pasta_cp_als_workspace_bytes. */
+pasta_status pasta_cp_als_workspace_bytes(const pasta_coo *X, uint32_t rank, size_t *bytes);
+pasta_status pasta_cp_als_sweep(const pasta_coo *X, float *const *d_factors, uint32_t rank, uint32_t ldf,
+                                float *d_lambda, double *d_fit, uint32_t *d_info, void *d_work, size_t work_bytes,
+                                void *stream);
+
 /* fp32 -> bf16 with round to nearest, ties to even (NaN stays NaN):
  * d_dst[i] = bf16(d_src[i]) for i < count, bf16 given as uint16 bits. */
 pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_t count, void *stream);

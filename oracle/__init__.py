@@ -206,3 +206,33 @@ def rel_fro(y, ystar) -> float:
     den = float(np.linalg.norm(ystar))
     num = float(np.linalg.norm(y - ystar))
     return num / den if den > 0 else float(np.linalg.norm(y))
+
+
+def cp_als_sweep(dims, inds, vals, factors, strategy: str = "seq"):
+    """One CP-ALS sweep in FP64 (alternating least squares for CPD, Section 3.1.1):
+    for each mode n, U_n = MTTKRP_n (Hadamard_{k!=n} U_k^T U_k)^{-1}, then the columns
+    of U_n are scaled to unit 2-norm (lambda = the norms). Returns (factors, lambda, fit)
+    with fit = 1 - ||X - [[lambda; U]]|| / ||X|| over the full tensor (X zero off the
+    nonzeros), computed from the Gram matrices and the last MTTKRP; ||X||^2 is the sum
+    of the squared values, so the coordinates are taken to be distinct."""
+    U = [np.array(f, dtype=np.float64) for f in factors]
+    N = len(dims)
+    lam = np.ones(U[0].shape[1])
+    M = None
+    for n in range(N):
+        M = mttkrp(dims, inds, vals, U, n, strategy)
+        V = np.ones((U[0].shape[1],) * 2)
+        for k in range(N):
+            if k != n:
+                V *= U[k].T @ U[k]
+        Un = np.linalg.solve(V, M.T).T
+        lam = np.linalg.norm(Un, axis=0)
+        U[n] = np.where(lam > 0, Un / np.where(lam > 0, lam, 1.0), 0.0)
+    x2 = float(np.dot(np.asarray(vals, np.float64), np.asarray(vals, np.float64)))
+    G = np.ones((U[0].shape[1],) * 2)
+    for k in range(N):
+        G *= U[k].T @ U[k]
+    model2 = float(lam @ G @ lam)
+    inner = float(np.sum(M * U[N - 1] * lam[None, :]))
+    fit = 1.0 - np.sqrt(max(0.0, x2 + model2 - 2.0 * inner)) / np.sqrt(x2) if x2 > 0 else 0.0
+    return U, lam, fit

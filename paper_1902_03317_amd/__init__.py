@@ -6,12 +6,14 @@ binding. The binding is loaded on first use of the API, so the input
 generator in :mod:`.synth` can be imported without it.
 """
 
-__all__ = ["Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16",
+__all__ = ["Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16", "cp_grad",
+           "cp_als_sweep", "mttkrp_atomic",
            "CPSample", "CPLoss", "lib"]
 
 
 def __getattr__(name):
-    if name in ("Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16"):
+    if name in ("Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16",
+                "cp_grad", "cp_als_sweep", "mttkrp_atomic"):
         from . import api
         return getattr(api, name)
     if name in ("CPSample", "CPLoss"):

@@ -228,3 +228,26 @@ def cast_bf16(src: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None
     check(lib.pasta_cast_f32_to_bf16(src.data_ptr(), out.data_ptr(), src.numel(), _stream(stream)),
           "pasta_cast_f32_to_bf16")
     return out
+
+
+def cp_als_sweep(X: Coo, factors: List[torch.Tensor], lam: Optional[torch.Tensor] = None, want_fit: bool = True,
+                 workspace: Optional[torch.Tensor] = None, stream=None):
+    """One CP-ALS sweep over every mode, updating the fp32 ``factors`` in place.
+
+    Returns (lambda [R] fp32, fit fp64 scalar tensor or None, info uint32 tensor:
+    1 if some normal-equation matrix was not positive definite)."""
+    ptrs, dt, R, ldf = _factor_args(X, factors, None)
+    if dt != _lib.PASTA_F32:
+        raise TypeError("CP-ALS updates fp32 factors")
+    if lam is None:
+        lam = torch.empty(R, dtype=torch.float32, device=X.device)
+    fit = torch.empty((), dtype=torch.float64, device=X.device) if want_fit else None
+    info = torch.empty(1, dtype=torch.int32, device=X.device)
+    if workspace is None:
+        n = ctypes.c_size_t()
+        check(lib.pasta_cp_als_workspace_bytes(X.handle, R, ctypes.byref(n)), "pasta_cp_als_workspace_bytes")
+        workspace = _scratch(n.value, X.device)
+    check(lib.pasta_cp_als_sweep(X.handle, ptrs, R, ldf, lam.data_ptr(), None if fit is None else fit.data_ptr(),
+                                 info.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream)),
+          "pasta_cp_als_sweep")
+    return lam, fit, info

@@ -652,6 +652,102 @@ pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_
     return PASTA_OK;
 }
 
+namespace {
+constexpr uint32_t kAlsSumsqParts = 1024;
+
+struct AlsLayout {
+    size_t M, mttkrp, grams, partial, vinv, inner, sumsq, xnorm2, flag, total;
+};
+
+AlsLayout als_layout(const pasta_coo *X, uint32_t R)
+{
+    AlsLayout L{};
+    uint64_t maxI = 0, maxnb = 0;
+    for (uint32_t k = 0; k < X->order; ++k) {
+        maxI = std::max<uint64_t>(maxI, X->dims[k]);
+        maxnb = std::max<uint64_t>(maxnb, gram_blocks(X->dims[k]));
+    }
+    size_t off = 0;
+    L.mttkrp = off;
+    off += align_up(mttkrp_ws_bound(X, R, PASTA_F32));
+    L.M = off;
+    off += align_up((size_t)maxI * R * sizeof(float));
+    L.grams = off;
+    off += align_up((size_t)X->order * R * R * sizeof(float));
+    L.partial = off;
+    off += align_up((size_t)maxnb * R * R * sizeof(float));
+    L.vinv = off;
+    off += align_up((size_t)R * R * sizeof(float));
+    L.inner = off;
+    off += align_up((size_t)maxnb * sizeof(double));
+    L.sumsq = off;
+    off += align_up((size_t)kAlsSumsqParts * sizeof(double));
+    L.xnorm2 = off;
+    off += align_up(sizeof(double));
+    L.flag = off;
+    off += align_up(sizeof(uint32_t));
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+pasta_status pasta_cp_als_workspace_bytes(const pasta_coo *X, uint32_t rank, size_t *bytes)
+{
+    if (!X || !bytes || rank == 0) return PASTA_EINVAL;
+    if (rank > 64) return PASTA_EUNSUPPORTED;
+    *bytes = als_layout(X, rank).total;
+    return PASTA_OK;
+}
+
+pasta_status pasta_cp_als_sweep(const pasta_coo *X, float *const *d_factors, uint32_t rank, uint32_t ldf,
+                                float *d_lambda, double *d_fit, uint32_t *d_info, void *d_work, size_t work_bytes,
+                                void *stream)
+{
+    if (!X || !d_factors || rank == 0 || ldf < rank || !d_lambda) return PASTA_EINVAL;
+    if (rank > 64) return PASTA_EUNSUPPORTED;
+    for (uint32_t k = 0; k < X->order; ++k)
+        if (!d_factors[k]) return PASTA_EINVAL;
+    const AlsLayout L = als_layout(X, rank);
+    if (!d_work || work_bytes < L.total || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(d_work);
+    float *M = reinterpret_cast<float *>(w + L.M);
+    float *grams = reinterpret_cast<float *>(w + L.grams);
+    float *partial = reinterpret_cast<float *>(w + L.partial);
+    float *vinv = reinterpret_cast<float *>(w + L.vinv);
+    double *inner = reinterpret_cast<double *>(w + L.inner);
+    double *xn2 = reinterpret_cast<double *>(w + L.xnorm2);
+    uint32_t *flag = d_info ? d_info : reinterpret_cast<uint32_t *>(w + L.flag);
+    const uint32_t RR = rank * rank;
+    HIPCHK(launch_fill_u32(flag, 0u, 1, st));
+    if (d_fit) {
+        if (X->nnz > 0) {
+            HIPCHK(launch_sumsq(X->vals, X->nnz, reinterpret_cast<double *>(w + L.sumsq), kAlsSumsqParts, xn2, st));
+        } else {
+            HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(xn2), 0u, 2, st));
+        }
+    }
+    for (uint32_t k = 0; k < X->order; ++k)
+        HIPCHK(launch_gram(d_factors[k], X->dims[k], ldf, rank, partial, grams + (uint64_t)k * RR, st));
+    const void *facs[kMaxOrder];
+    for (uint32_t k = 0; k < X->order; ++k) facs[k] = d_factors[k];
+    for (uint32_t n = 0; n < X->order; ++n) {
+        pasta_status s = run_mttkrp(X, n, facs, PASTA_F32, rank, ldf, nullptr, 1.0f, M, rank, w + L.mttkrp,
+                                    L.M - L.mttkrp, false, nullptr, st);
+        if (s != PASTA_OK) return s;
+        HIPCHK(launch_als_solve(grams, X->order, n, rank, vinv, flag, st));
+        HIPCHK(launch_als_update(M, rank, vinv, rank, X->dims[n], d_factors[n], ldf, st));
+        HIPCHK(launch_normalize(d_factors[n], X->dims[n], ldf, rank, partial, d_lambda, st));
+        HIPCHK(launch_gram(d_factors[n], X->dims[n], ldf, rank, partial, grams + (uint64_t)n * RR, st));
+    }
+    if (d_fit) {
+        const uint32_t last = X->order - 1;
+        HIPCHK(launch_fit(M, rank, d_factors[last], ldf, d_lambda, X->dims[last], rank, grams, X->order, inner, xn2,
+                          d_fit, st));
+    }
+    return PASTA_OK;
+}
+
 pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop)
 {
     g_ev_start = static_cast<hipEvent_t>(ev_start);

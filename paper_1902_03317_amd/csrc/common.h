@@ -237,6 +237,20 @@ hipError_t launch_scale(float *x, uint64_t n, const double *alpha, hipStream_t s
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint16_t *shadow, uint64_t n, float lr,
                        float b1, float b2, float eps, uint32_t step, hipStream_t st);
 
+// CP-ALS (als.hip)
+uint32_t gram_blocks(uint64_t I);
+hipError_t launch_gram(const float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *G, hipStream_t st);
+hipError_t launch_als_solve(const float *grams, uint32_t order, uint32_t mode, uint32_t R, float *Vinv,
+                            uint32_t *flag, hipStream_t st);
+hipError_t launch_als_update(const float *M, uint32_t ldm, const float *Vinv, uint32_t R, uint64_t I, float *U,
+                             uint32_t ldu, hipStream_t st);
+hipError_t launch_normalize(float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *lambda,
+                            hipStream_t st);
+hipError_t launch_fit(const float *M, uint32_t ldm, const float *U, uint32_t ldu, const float *lambda, uint64_t I,
+                      uint32_t R, const float *grams, uint32_t order, double *inner_partial,
+                      const double *xnorm2, double *fit, hipStream_t st);
+hipError_t launch_sumsq(const float *x, uint64_t n, double *partial, uint32_t nparts, double *out, hipStream_t st);
+
 constexpr uint32_t kSortThreads = 256;
 constexpr uint32_t kSortItems = 16;
 constexpr uint32_t kSortTile = kSortThreads * kSortItems;  // keys per sort tile

@@ -350,3 +350,45 @@ def test_pins_reject_planted_mistakes(mutant):
         marg = np.bincount(inds[n], weights=vals, minlength=dims[n])
         ok &= np.allclose(_mttkrp_loops(dims, inds, vals, ones, n, mutant)[:, 0], marg)
     assert ok == (mutant is None)
+
+
+def test_cp_als_update_is_the_least_squares_solution(oracle_lib):
+    """Each mode update of the ALS sweep solves min ||X_(n) - U_n (KRP of the others)^T||_F:
+    checked against numpy lstsq on the dense unfolding and the explicit Khatri-Rao product."""
+    rng = np.random.default_rng(23)
+    dims = (6, 5, 4)
+    lin = rng.choice(120, 70, replace=False)  # distinct coordinates: the fit's norm is the dense one
+    inds = np.stack(np.unravel_index(lin, dims)).astype(np.uint32)
+    vals = rng.standard_normal(70)
+    U0 = rand_factors(rng, dims, 3)
+    X = brute.dense(dims, inds, vals)
+    U, lam, fit = oracle.cp_als_sweep(dims, inds, vals, U0)
+    # replay the sweep mode by mode with lstsq on the unfolding
+    W = [u.copy() for u in U0]
+    for n in range(3):
+        K = brute.khatri_rao_chain([W[k] for k in reversed(range(3)) if k != n])
+        Un = np.linalg.lstsq(K, brute.unfold(X, n).T, rcond=None)[0].T
+        ln = np.linalg.norm(Un, axis=0)
+        W[n] = Un / ln
+    for n in range(3):
+        assert rel(U[n], W[n]) <= 1e-10
+    assert rel(lam, ln) <= 1e-10
+    # the fit formula against the dense residual
+    model = brute.cp_full([W[0], W[1], W[2] * ln[None, :]])
+    want = 1.0 - np.linalg.norm(X - model) / np.linalg.norm(X)
+    assert abs(fit - want) <= 1e-10
+
+
+def test_cp_als_recovers_a_planted_model(oracle_lib):
+    """A fully observed exact rank-3 tensor: a few sweeps from a random start drive the
+    fit to 1 (the model is recovered)."""
+    rng = np.random.default_rng(24)
+    dims = (8, 7, 6)
+    A = rand_factors(rng, dims, 3)
+    X = brute.cp_full(A)
+    inds = np.stack(np.unravel_index(np.arange(X.size), dims)).astype(np.uint32)
+    U = rand_factors(rng, dims, 3)
+    fit = 0.0
+    for _ in range(60):
+        U, lam, fit = oracle.cp_als_sweep(dims, inds, X.reshape(-1), U)
+    assert fit > 1 - 1e-6
