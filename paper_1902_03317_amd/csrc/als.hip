@@ -10,7 +10,7 @@
 namespace pasta {
 
 constexpr int kAlsMaxRank = 64;
-constexpr uint32_t kGramRows = 2048;  // rows of U per partial Gram
+constexpr uint32_t kGramRows = 256;  // rows of U per partial Gram
 
 // partial[b][r1][r2] = sum over rows i of block b of U[i, r1] * U[i, r2]
 __global__ __launch_bounds__(256) void gram_partial_kernel(const float *__restrict__ U, uint64_t I, uint32_t ld,
@@ -128,30 +128,20 @@ __global__ __launch_bounds__(256) void als_update_kernel(const float *__restrict
     }
 }
 
-// partial[b][r] = sum over rows of block b of U[i, r]^2   (rows per block: kGramRows)
-__global__ void colnorm_partial_kernel(const float *__restrict__ U, uint64_t I, uint32_t ld, uint32_t R,
-                                       float *__restrict__ partial)
+// From the Gram matrix of the updated (unnormalised) U_n: lambda_r = sqrt(G[r][r]),
+// and the Gram of the normalised columns, G[a][b] / (lambda_a lambda_b).
+__global__ void gram_normalize_kernel(float *__restrict__ G, uint32_t R, float *__restrict__ lambda)
 {
-    const uint64_t r0 = (uint64_t)blockIdx.x * kGramRows;
-    const uint64_t r1 = r0 + kGramRows < I ? r0 + kGramRows : I;
+    __shared__ float l[kAlsMaxRank];
     for (uint32_t c = threadIdx.x; c < R; c += blockDim.x) {
-        float s = 0.0f;
-        for (uint64_t i = r0; i < r1; ++i) {
-            const float v = U[i * ld + c];
-            s += v * v;
-        }
-        partial[(uint64_t)blockIdx.x * R + c] = s;
+        const float d = G[c * R + c];
+        l[c] = d > 0.0f ? sqrtf(d) : 0.0f;
+        lambda[c] = l[c];
     }
-}
-
-// lambda[r] = sqrt(sum_b partial[b][r]); then U[:, r] /= lambda[r] (zero columns stay zero)
-__global__ void colnorm_finish_kernel(const float *__restrict__ partial, uint32_t nb, uint32_t R,
-                                      float *__restrict__ lambda)
-{
-    for (uint32_t c = threadIdx.x; c < R; c += blockDim.x) {
-        float s = 0.0f;
-        for (uint32_t b = 0; b < nb; ++b) s += partial[(uint64_t)b * R + c];
-        lambda[c] = sqrtf(s);
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < R * R; p += blockDim.x) {
+        const float la = l[p / R], lb = l[p % R];
+        G[p] = (la > 0.0f && lb > 0.0f) ? G[p] / (la * lb) : 0.0f;
     }
 }
 
@@ -264,12 +254,12 @@ hipError_t launch_als_update(const float *M, uint32_t ldm, const float *Vinv, ui
     return hipGetLastError();
 }
 
-hipError_t launch_normalize(float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *lambda,
+hipError_t launch_normalize(float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *G, float *lambda,
                             hipStream_t st)
 {
-    const uint32_t nb = gram_blocks(I);
-    colnorm_partial_kernel<<<nb, 64, 0, st>>>(U, I, ld, R, partial);
-    colnorm_finish_kernel<<<1, 64, 0, st>>>(partial, nb, R, lambda);
+    hipError_t e = launch_gram(U, I, ld, R, partial, G, st);
+    if (e != hipSuccess) return e;
+    gram_normalize_kernel<<<1, 256, 0, st>>>(G, R, lambda);
     const uint64_t total = I * R;
     unsigned g = (unsigned)((total + 255) / 256);
     if (g > 16384) g = 16384;

@@ -222,11 +222,10 @@ bool plan_mttkrp(const pasta_coo *X, uint32_t rank, KernelShape s, MttkrpPlan &p
 // Worst case over kernel shapes for a rank: the contiguous shape has the most chunks.
 size_t mttkrp_ws_bound(const pasta_coo *X, uint32_t rank, pasta_dtype dt)
 {
-    size_t best = 0;
-    KernelShape shapes[2];
     const uint32_t vec = dt == PASTA_F32 ? 4 : 8;
-    shapes[0] = {(int)vec, (int)next_pow2(std::max<uint32_t>(1, (rank + vec - 1) / vec)), false};
-    shapes[1] = {4, 64, true};
+    KernelShape shapes[2] = {{(int)vec, (int)next_pow2(std::max<uint32_t>(1, (rank + vec - 1) / vec)), false},
+                             {4, 64, true}};
+    size_t best = 0;
     for (auto &s : shapes) {
         if (s.lanes > 16 && !s.strided) continue;
         MttkrpPlan p;
@@ -737,8 +736,8 @@ pasta_status pasta_cp_als_sweep(const pasta_coo *X, float *const *d_factors, uin
         if (s != PASTA_OK) return s;
         HIPCHK(launch_als_solve(grams, X->order, n, rank, vinv, flag, st));
         HIPCHK(launch_als_update(M, rank, vinv, rank, X->dims[n], d_factors[n], ldf, st));
-        HIPCHK(launch_normalize(d_factors[n], X->dims[n], ldf, rank, partial, d_lambda, st));
-        HIPCHK(launch_gram(d_factors[n], X->dims[n], ldf, rank, partial, grams + (uint64_t)n * RR, st));
+        HIPCHK(launch_normalize(d_factors[n], X->dims[n], ldf, rank, partial, grams + (uint64_t)n * RR, d_lambda,
+                                st));
     }
     if (d_fit) {
         const uint32_t last = X->order - 1;

@@ -244,7 +244,8 @@ hipError_t launch_als_solve(const float *grams, uint32_t order, uint32_t mode, u
                             uint32_t *flag, hipStream_t st);
 hipError_t launch_als_update(const float *M, uint32_t ldm, const float *Vinv, uint32_t R, uint64_t I, float *U,
                              uint32_t ldu, hipStream_t st);
-hipError_t launch_normalize(float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *lambda,
+// G <- Gram of U; lambda <- its column norms; U and G <- their normalised forms
+hipError_t launch_normalize(float *U, uint64_t I, uint32_t ld, uint32_t R, float *partial, float *G, float *lambda,
                             hipStream_t st);
 hipError_t launch_fit(const float *M, uint32_t ldm, const float *U, uint32_t ldu, const float *lambda, uint64_t I,
                       uint32_t R, const float *grams, uint32_t order, double *inner_partial,
