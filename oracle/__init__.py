@@ -15,7 +15,13 @@ Section 5.2 Alg. 6 of the suite):
   * ``sort_perm`` / ``mode_orders`` / ``rowptr``: stable orders of the
     nonzeros by one mode, the chained per-mode orders, and the row offsets of
     a sorted stream (a library sort as the step);
-  * ``bf16_round``: float32 -> bfloat16, round to nearest, ties to even.
+  * ``bf16_round``: float32 -> bfloat16, round to nearest, ties to even;
+  * ``fiber_order`` / ``fibers``: the mode-n fibers (Section 3: every index
+    fixed except i_n) that hold nonzeros, and the order that makes each one a
+    contiguous run (the pre-processing step of Algs. 4 and 5);
+  * ``ttm``: Y = X x_n U (Section 4.4, eq. ttm, U of shape I_n x R), kept
+    semi-sparse as one dense R-vector per fiber (Alg. 5);
+  * ``ttv``: Y = X x_n v (Section 4.3), one value per fiber (Alg. 4).
 """
 from __future__ import annotations
 
@@ -236,3 +242,62 @@ def cp_als_sweep(dims, inds, vals, factors, strategy: str = "seq"):
     inner = float(np.sum(M * U[N - 1] * lam[None, :]))
     fit = 1.0 - np.sqrt(max(0.0, x2 + model2 - 2.0 * inner)) / np.sqrt(x2) if x2 > 0 else 0.0
     return U, lam, fit
+
+
+def fiber_order(inds, mode: int) -> np.ndarray:
+    """Order of the nonzeros in which every mode-``mode`` fiber is one contiguous run:
+    lexicographic in the other modes' indices taken in mode order, then i_mode, then
+    caller position (``np.lexsort`` is stable; its last key is the primary one)."""
+    inds = np.asarray(inds)
+    N = inds.shape[0]
+    keys = [inds[mode]] + [inds[k] for k in reversed(range(N)) if k != mode]
+    return np.lexsort(keys).astype(np.uint32)
+
+
+def fibers(inds, mode: int):
+    """(order, fptr, coords) of the mode-``mode`` fibers that hold nonzeros.
+
+    order: ``fiber_order``; fptr[f]: position in that order of the first nonzero
+    of fiber f, fptr[nfibs] = nnz; coords: [N-1, nfibs], the fixed indices of
+    each fiber, modes in increasing order with ``mode`` left out."""
+    inds = np.asarray(inds)
+    N, M = inds.shape
+    other = [k for k in range(N) if k != mode]
+    o = fiber_order(inds, mode)
+    s = inds[:, o]
+    if M == 0:
+        return o, np.zeros(1, np.uint32), np.zeros((N - 1, 0), np.uint32)
+    new = np.ones(M, dtype=bool)
+    new[1:] = np.any(s[other][:, 1:] != s[other][:, :-1], axis=0)
+    starts = np.flatnonzero(new)
+    fptr = np.append(starts, M).astype(np.uint32)
+    return o, fptr, s[other][:, starts].astype(np.uint32)
+
+
+def ttm(dims, inds, vals, U, mode: int):
+    """Sparse TTM, Y = X x_n U with U of shape I_n x R (the paper's orientation,
+    eq. ttm), FP64. Alg. 5: for every fiber f, Y[f, :] = sum over the nonzeros m
+    of the fiber of x_m U[i_n(m), :]. Returns (fptr, coords, Y[nfibs, R])."""
+    inds = np.asarray(inds)
+    U = np.asarray(U, dtype=np.float64)
+    if U.ndim != 2 or U.shape[0] != int(dims[mode]):
+        raise ValueError("U must be [dims[mode], R]")
+    if inds.size and int(inds[mode].max()) >= int(dims[mode]):
+        raise ValueError("index out of range")
+    o, fptr, coords = fibers(inds, mode)
+    x = np.asarray(vals, dtype=np.float64)[o]
+    contrib = x[:, None] * U[inds[mode][o].astype(np.int64)]
+    nf = fptr.size - 1
+    Y = np.add.reduceat(contrib, fptr[:-1].astype(np.int64), axis=0) if nf else np.zeros((0, U.shape[1]))
+    return fptr, coords, Y
+
+
+def ttv(dims, inds, vals, v, mode: int):
+    """Sparse TTV, Y = X x_n v (Section 4.3), FP64. Alg. 4: for every fiber f,
+    Y[f] = sum over the nonzeros m of the fiber of x_m v[i_n(m)].
+    Returns (fptr, coords, Y[nfibs])."""
+    v = np.asarray(v, dtype=np.float64)
+    if v.ndim != 1:
+        raise ValueError("v must be a vector")
+    fptr, coords, Y = ttm(dims, inds, vals, v[:, None], mode)
+    return fptr, coords, Y[:, 0]
