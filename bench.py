@@ -62,6 +62,17 @@ def bytes_alg(N: int, R: int, sf: int, nnz: int, I_n: int) -> int:
     return nnz * bytes_alg_per_nnz(N, R, sf) + 4 * R * I_n
 
 
+def bytes_ttm(R: int, sf: int, nnz: int, nfibs: int) -> int:
+    """Sparse TTM over the fiber-ordered stream: fiber id, i_n and value per nonzero,
+    one gathered R-row of U per nonzero (no reuse), one R-row written per fiber."""
+    return nnz * (12 + R * sf) + 4 * R * nfibs
+
+
+def bytes_ttv(nnz: int, nfibs: int) -> int:
+    """Sparse TTV: fiber id, i_n, value and the gathered v entry per nonzero, one value per fiber."""
+    return nnz * 16 + 4 * nfibs
+
+
 def bytes_compulsory(dims, R: int, sf: int, nnz: int, n: int) -> int:
     """Every byte touched once: the stream, every other factor once, the output once."""
     N = len(dims)
@@ -363,6 +374,50 @@ def main():
             hip.record(e1, s_ptr)
             ts.append(hip.ms(e0, e1))
         line["cp_als_sweep_ms"] = round(sorted(ts)[len(ts) // 2], 4)
+    if do_cp:
+        # sparse TTM (rank R, fp32 U) and TTV along every mode (Algs. 5 and 4), timed apart:
+        # fiber pre-processing once per mode, then call and main-kernel times (median of 10)
+        Uf = [torch.from_numpy(u).to(dev) for u in U]
+        fib = {"ttm": ([], []), "ttv": ([], [])}
+        pre_f, nfibs = [], []
+        for n in range(N):
+            e0, e1 = hip.event(), hip.event()
+            hip.record(e0, s_ptr)
+            F = api.Fibers(X, n)
+            hip.record(e1, s_ptr)
+            pre_f.append(hip.ms(e0, e1))
+            nfibs.append(F.nfibs)
+            y = torch.empty((F.nfibs, R), dtype=torch.float32, device=dev)
+            yv = torch.empty(F.nfibs, dtype=torch.float32, device=dev)
+            ws_t = torch.empty(max(api.ttm_workspace_bytes(F, R), api.ttv_workspace_bytes(F)), dtype=torch.uint8,
+                               device=dev)
+            v = Uf[n][:, 0].contiguous()
+            runs = {"ttm": lambda: api.ttm(F, Uf[n], out=y, workspace=ws_t),
+                    "ttv": lambda: api.ttv(F, v, out=yv, workspace=ws_t)}
+            for name, fn in runs.items():
+                fn()
+                fn()
+                calls, kerns = [], []
+                for _ in range(10):
+                    k0, k1, c0, c1 = hip.event(), hip.event(), hip.event(), hip.event()
+                    plib.pasta_arm_kernel_events(k0, k1)
+                    hip.record(c0, s_ptr)
+                    fn()
+                    hip.record(c1, s_ptr)
+                    calls.append(hip.ms(c0, c1))
+                    kerns.append(hip.ms(k0, k1))
+                fib[name][0].append(sorted(calls)[5])
+                fib[name][1].append(sorted(kerns)[5])
+            del F, y, yv, ws_t
+        for name in ("ttm", "ttv"):
+            calls, kerns = fib[name]
+            algb = [bytes_ttm(R, 4, M, nf) if name == "ttm" else bytes_ttv(M, nf) for nf in nfibs]
+            line[name] = {"gnnz_s": round(N * M / (sum(calls) * 1e-3) / 1e9, 3),
+                          "ms_per_mode": [round(c, 4) for c in calls], "kernel_ms": [round(k, 4) for k in kerns],
+                          "hbm_frac": round(sum(algb) / (sum(kerns) * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                          "bytes_alg_per_mode": algb, "nfibs": nfibs}
+        line["ttm"]["rank"] = R
+        line["fibers_preprocess_ms"] = [round(t, 3) for t in pre_f]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (m, inds_s, vals_s, outs_o) = cpu_baseline(coo, U)

@@ -9,7 +9,8 @@
  *
  * for every row i of mode n (rows without nonzeros are zero), plus the
  * sampled CP model and its residual-weighted MTTKRP gradient (CP
- * decomposition, Section 3.1.1).
+ * decomposition, Section 3.1.1), a CP-ALS sweep, and the fiber-based sparse
+ * TTM and TTV of Sections 4.3-4.4 (Algs. 4 and 5).
  *
  * Conventions shared by every entry point
  *   - Coordinates are 0-based (the COO example of Section 5.1); indices are
@@ -23,7 +24,8 @@
  *     call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     All work is enqueued on it and the call returns without waiting,
- *     except pasta_coo_create, which waits once for its index check.
+ *     except pasta_coo_create, which waits once for its index check, and
+ *     pasta_fibers_create, which waits once to read the fiber count.
  *   - Argument errors are reported synchronously through the return value
  *     and nothing is enqueued; the library never aborts or throws.
  *   - Calls that share a handle may run concurrently only if they do not
@@ -67,9 +69,11 @@ pasta_status pasta_coo_workspace_bytes(uint32_t order, const uint64_t *dims, uin
 
 /* Preprocess a COO tensor (the sorting and fiber/row pointers the suite
  * builds before its kernels, Section 5.2): checks every coordinate against
- * its dimension, then for every mode n stably sorts the nonzeros by i_n
- * (ties keep the caller's order), stores the sorted copy, the permutation
- * and the row offsets in the workspace.
+ * its dimension, then for every mode n sorts the nonzeros by i_n and stores
+ * the sorted copy, the permutation and the row offsets in the workspace.
+ * Mode n's order is lexicographic in (i_n, i_{n-1}, ..., i_0), then i_{N-1}
+ * (for n < N-1), then caller position: each mode's order is the stable sort
+ * by i_n of the previous mode's order.
  *   d_inds  host array of `order` device pointers; d_inds[k][m] = i_k(m).
  *   d_vals  device array of nnz fp32 values.
  *   d_workspace  >= pasta_coo_workspace_bytes, 256-byte aligned.
@@ -179,8 +183,9 @@ pasta_status pasta_cp_als_sweep(const pasta_coo *X, float *const *d_factors, uin
  * d_dst[i] = bf16(d_src[i]) for i < count, bf16 given as uint16 bits. */
 pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_t count, void *stream);
 
-/* Measurement hook: the next MTTKRP main kernel that this thread launches
- * (from pasta_mttkrp or the first mode of pasta_cp_grad) records ev_start
+/* Measurement hook: the next main kernel that this thread launches (from
+ * pasta_mttkrp, the first mode of pasta_cp_grad, pasta_ttm or pasta_ttv)
+ * records ev_start
  * (a hipEvent_t) on its stream right before the launch and ev_stop right
  * after it, so their elapsed time is that kernel alone. The pair is used
  * once and then disarmed; NULL disarms. Calls with nnz = 0 leave it armed. */
@@ -200,6 +205,60 @@ pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, 
 pasta_status pasta_adam_step(float *d_param, const float *d_grad, float *d_m, float *d_v, uint16_t *d_shadow_bf16,
                              uint64_t count, float lr, float beta1, float beta2, float eps, uint32_t step,
                              void *stream);
+
+/* ---- Mode-n fibers, sparse TTM and TTV ---------------------------------
+ * A mode-n fiber fixes every index but i_n (Section 3). TTV (Section 4.3)
+ * and TTM (Section 4.4, eq. ttm) contract mode n with a vector v (I_n) or a
+ * matrix U (I_n x R, the paper's orientation: row i_n holds R entries), and
+ * every fiber of X that holds nonzeros gives one output entry (TTV) or one
+ * dense R-vector (TTM): the result keeps the other modes sparse (Algs. 4 and
+ * 5, which size the output by the fiber count nfibs). */
+typedef struct pasta_fibers pasta_fibers;
+
+/* Bytes of device workspace for pasta_fibers_create on this mode. */
+pasta_status pasta_fibers_workspace_bytes(const pasta_coo *X, uint32_t mode, size_t *bytes);
+
+/* The pre-processing step of Algs. 4 and 5: reorder the nonzeros so that
+ * each mode-`mode` fiber is one contiguous run, and find nfibs, the run
+ * offsets (fptr) and each fiber's coordinates. The fiber order is
+ * lexicographic in the other modes' indices (in mode order), then i_mode,
+ * then caller position; fibers are numbered 0..nfibs-1 in that order.
+ * Reads X's preprocessed arrays on the stream; the handle then depends only
+ * on d_workspace (>= pasta_fibers_workspace_bytes, 256-byte aligned), not on
+ * X. Waits for the stream once. */
+pasta_status pasta_fibers_create(const pasta_coo *X, uint32_t mode, void *d_workspace, size_t workspace_bytes,
+                                 void *stream, pasta_fibers **out);
+pasta_status pasta_fibers_destroy(pasta_fibers *F);
+/* Mode and number of fibers holding nonzeros. */
+pasta_status pasta_fibers_info(const pasta_fibers *F, uint32_t *mode, uint64_t *nfibs);
+/* Device views (read-only; any output may be NULL):
+ *   d_fptr[f]      first position of fiber f in fiber order (nfibs + 1
+ *                  entries, d_fptr[nfibs] = nnz);
+ *   d_coords       host array of order - 1 pointers: the fixed indices of
+ *                  each fiber (nfibs each), modes in order without `mode`;
+ *   d_perm[p]      caller position of the p-th nonzero in fiber order;
+ *   d_fid[p]       fiber of the p-th nonzero in fiber order. */
+pasta_status pasta_fibers_view(const pasta_fibers *F, const uint32_t **d_fptr, const uint32_t **d_coords,
+                               const uint32_t **d_perm, const uint32_t **d_fid);
+
+/* Sparse TTM, Y = X x_mode U (Alg. 5): for every fiber f,
+ *   d_out[f][r] = sum over the nonzeros m of fiber f of x(m) * U[i_mode(m)][r].
+ *   d_U    I_mode x ldu, fp32 or bf16 (fp32 arithmetic); rank R <= 256.
+ *   d_out  nfibs x ldo fp32, overwritten; ldo >= R.
+ *   d_work >= pasta_ttm_workspace_bytes, 256-byte aligned.
+ * Deterministic (same inputs, same bits). */
+pasta_status pasta_ttm_workspace_bytes(const pasta_fibers *F, uint32_t rank, pasta_dtype dtype, size_t *bytes);
+pasta_status pasta_ttm(const pasta_fibers *F, const void *d_U, pasta_dtype dtype, uint32_t rank, uint32_t ldu,
+                       float *d_out, uint32_t ldo, void *d_work, size_t work_bytes, void *stream);
+
+/* Sparse TTV, Y = X x_mode v (Alg. 4): for every fiber f,
+ *   d_out[f] = sum over the nonzeros m of fiber f of x(m) * v[i_mode(m)].
+ *   d_v    I_mode fp32;  d_out  nfibs fp32, overwritten.
+ *   d_work >= pasta_ttv_workspace_bytes, 256-byte aligned.
+ * Deterministic. */
+pasta_status pasta_ttv_workspace_bytes(const pasta_fibers *F, size_t *bytes);
+pasta_status pasta_ttv(const pasta_fibers *F, const float *d_v, float *d_out, void *d_work, size_t work_bytes,
+                       void *stream);
 
 /* Text of a status code (static storage). */
 const char *pasta_status_str(pasta_status s);

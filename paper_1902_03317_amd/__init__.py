@@ -1,4 +1,5 @@
-"""MI355X-native COO MTTKRP (mode-n matricized tensor times Khatri-Rao product).
+"""MI355X-native COO MTTKRP (mode-n matricized tensor times Khatri-Rao product),
+with the CP model and CP-ALS built on it and the fiber-based sparse TTM / TTV.
 
 The compute path lives in ``libpasta.so`` (HIP kernels for gfx950 behind a
 C ABI, declared in ``include/pasta.h``); this package is its thin Python
@@ -7,13 +8,13 @@ generator in :mod:`.synth` can be imported without it.
 """
 
 __all__ = ["Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16", "cp_grad",
-           "cp_als_sweep", "mttkrp_atomic",
+           "cp_als_sweep", "mttkrp_atomic", "Fibers", "ttm", "ttv",
            "CPSample", "CPLoss", "lib"]
 
 
 def __getattr__(name):
     if name in ("Coo", "mttkrp", "mttkrp_workspace_bytes", "cp_sample", "cp_residual_loss", "cast_bf16",
-                "cp_grad", "cp_als_sweep", "mttkrp_atomic"):
+                "cp_grad", "cp_als_sweep", "mttkrp_atomic", "Fibers", "ttm", "ttv"):
         from . import api
         return getattr(api, name)
     if name in ("CPSample", "CPLoss"):

@@ -51,6 +51,15 @@ SIGNATURES = {
     "pasta_cp_als_workspace_bytes": [P, U32, ctypes.POINTER(SZ)],
     "pasta_cp_als_sweep": [P, P, U32, U32, P, P, P, P, SZ, P],
     "pasta_adam_step": [P, P, P, P, P, U64, F32, F32, F32, F32, U32, P],
+    "pasta_fibers_workspace_bytes": [P, U32, ctypes.POINTER(SZ)],
+    "pasta_fibers_create": [P, U32, P, SZ, P, ctypes.POINTER(P)],
+    "pasta_fibers_destroy": [P],
+    "pasta_fibers_info": [P, ctypes.POINTER(U32), ctypes.POINTER(U64)],
+    "pasta_fibers_view": [P, ctypes.POINTER(P), P, ctypes.POINTER(P), ctypes.POINTER(P)],
+    "pasta_ttm_workspace_bytes": [P, U32, ctypes.c_int, ctypes.POINTER(SZ)],
+    "pasta_ttm": [P, P, ctypes.c_int, U32, U32, P, U32, P, SZ, P],
+    "pasta_ttv_workspace_bytes": [P, ctypes.POINTER(SZ)],
+    "pasta_ttv": [P, P, P, P, SZ, P],
 }
 
 for _name, _args in SIGNATURES.items():

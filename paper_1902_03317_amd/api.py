@@ -251,3 +251,110 @@ def cp_als_sweep(X: Coo, factors: List[torch.Tensor], lam: Optional[torch.Tensor
                                  info.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream)),
           "pasta_cp_als_sweep")
     return lam, fit, info
+
+
+class Fibers:
+    """The mode-``mode`` fibers of a preprocessed tensor (Algs. 4 and 5's
+    pre-processing): the nonzeros reordered so that each fiber (every index
+    fixed but i_mode) is one run, numbered in lexicographic order of the other
+    modes' indices. Owns its workspace; does not keep ``X`` alive."""
+
+    def __init__(self, X: Coo, mode: int, stream=None, workspace: Optional[torch.Tensor] = None):
+        if not (0 <= mode < X.order):
+            raise ValueError("mode out of range")
+        self.mode = int(mode)
+        self.order = X.order
+        self.dims = X.dims
+        self.nnz = X.nnz
+        self.device = X.device
+        nbytes = ctypes.c_size_t()
+        check(lib.pasta_fibers_workspace_bytes(X.handle, self.mode, ctypes.byref(nbytes)),
+              "pasta_fibers_workspace_bytes")
+        if workspace is not None and workspace.dtype == torch.uint8 and workspace.numel() >= nbytes.value:
+            self.workspace = workspace
+        else:
+            self.workspace = _scratch(nbytes.value, self.device)
+        h = ctypes.c_void_p()
+        check(lib.pasta_fibers_create(X.handle, self.mode, self.workspace.data_ptr(), self.workspace.numel(),
+                                      _stream(stream), ctypes.byref(h)), "pasta_fibers_create")
+        self._h = h
+        nf = ctypes.c_uint64()
+        check(lib.pasta_fibers_info(h, None, ctypes.byref(nf)), "pasta_fibers_info")
+        self.nfibs = int(nf.value)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.pasta_fibers_destroy(h)
+            self._h = None
+
+    def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
+        off = ptr - self.workspace.data_ptr()
+        esz = torch.tensor([], dtype=dtype).element_size()
+        return self.workspace[off: off + count * esz].view(dtype)
+
+    def view(self):
+        """(fptr [nfibs+1], coords [order-1 tensors of nfibs], perm [nnz], fid [nnz]) as int32 views."""
+        fptr, perm, fid = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        coords = (ctypes.c_void_p * max(1, self.order - 1))()
+        check(lib.pasta_fibers_view(self._h, ctypes.byref(fptr), coords, ctypes.byref(perm), ctypes.byref(fid)),
+              "pasta_fibers_view")
+        nf, M = self.nfibs, self.nnz
+        return (self._view(fptr.value, nf + 1, torch.int32),
+                [self._view(coords[q], nf, torch.int32) for q in range(self.order - 1)],
+                self._view(perm.value, M, torch.int32), self._view(fid.value, M, torch.int32))
+
+
+def ttm_workspace_bytes(F: Fibers, rank: int, dtype=torch.float32) -> int:
+    n = ctypes.c_size_t()
+    check(lib.pasta_ttm_workspace_bytes(F.handle, int(rank), _DT[dtype], ctypes.byref(n)), "pasta_ttm_workspace_bytes")
+    return n.value
+
+
+def ttm(F: Fibers, U: torch.Tensor, out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+        stream=None) -> torch.Tensor:
+    """Sparse TTM (Alg. 5): out[f, :] = sum over fiber f's nonzeros of x * U[i_mode, :]; fp32 [nfibs, R].
+    U is [dims[mode], R] (fp32 or bf16, unit column stride)."""
+    if not U.is_cuda or U.dim() != 2 or U.stride(1) != 1 or U.dtype not in _DT:
+        raise ValueError("U must be a 2-D float32/bfloat16 CUDA tensor with unit column stride")
+    if U.shape[0] != F.dims[F.mode]:
+        raise ValueError(f"U has {U.shape[0]} rows, mode size is {F.dims[F.mode]}")
+    R = int(U.shape[1])
+    ldu = int(max(U.stride(0), R))
+    if out is None:
+        out = torch.empty((F.nfibs, R), dtype=torch.float32, device=F.device)
+    if out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != F.nfibs or out.shape[1] < R \
+            or out.stride(1) != 1:
+        raise ValueError("out must be float32 [nfibs, >= R] with unit column stride")
+    ws = workspace if workspace is not None else _scratch(ttm_workspace_bytes(F, R, U.dtype), F.device)
+    check(lib.pasta_ttm(F.handle, U.data_ptr(), _DT[U.dtype], R, ldu, out.data_ptr(),
+                        int(max(out.stride(0), out.shape[1])), ws.data_ptr(), ws.numel(), _stream(stream)),
+          "pasta_ttm")
+    return out
+
+
+def ttv_workspace_bytes(F: Fibers) -> int:
+    n = ctypes.c_size_t()
+    check(lib.pasta_ttv_workspace_bytes(F.handle, ctypes.byref(n)), "pasta_ttv_workspace_bytes")
+    return n.value
+
+
+def ttv(F: Fibers, v: torch.Tensor, out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+        stream=None) -> torch.Tensor:
+    """Sparse TTV (Alg. 4): out[f] = sum over fiber f's nonzeros of x * v[i_mode]; fp32 [nfibs]."""
+    if not v.is_cuda or v.dtype != torch.float32 or v.dim() != 1 or not v.is_contiguous():
+        raise ValueError("v must be a contiguous float32 CUDA vector")
+    if v.numel() != F.dims[F.mode]:
+        raise ValueError(f"v has {v.numel()} entries, mode size is {F.dims[F.mode]}")
+    if out is None:
+        out = torch.empty(F.nfibs, dtype=torch.float32, device=F.device)
+    if out.dtype != torch.float32 or out.numel() != F.nfibs or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [nfibs] tensor")
+    ws = workspace if workspace is not None else _scratch(ttv_workspace_bytes(F), F.device)
+    check(lib.pasta_ttv(F.handle, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
+          "pasta_ttv")
+    return out

@@ -32,7 +32,8 @@ FLAGS = [
 def _jobs():
     srcs = [(os.path.join(CSRC, "api.hip"), "api.o", []),
             (os.path.join(CSRC, "preprocess.hip"), "preprocess.o", []),
-            (os.path.join(CSRC, "als.hip"), "als.o", [])]
+            (os.path.join(CSRC, "als.hip"), "als.o", []),
+            (os.path.join(CSRC, "fibers.hip"), "fibers.o", [])]
     for n in ORDERS:
         srcs.append((os.path.join(CSRC, "kernels_order.hip"), f"kernels_order{n}.o", [f"-DPASTA_NM1={n - 1}"]))
     return srcs

@@ -7,6 +7,7 @@
 
 #include "../../include/pasta.h"
 #include "common.h"
+#include "fibers.h"
 
 using namespace pasta;
 
@@ -22,6 +23,19 @@ struct pasta_coo {
         uint32_t *perm;
         uint32_t *rowptr;
     } mode[kMaxOrder];
+};
+
+// Mode-n fibers of a tensor (pasta_fibers_create): the nonzeros reordered so
+// that each fiber is one contiguous run, with the run offsets and coordinates.
+struct pasta_fibers {
+    uint32_t order, mode;
+    uint64_t nnz, nfibs, dim;
+    const uint32_t *fid;   // fiber of each nonzero, fiber order
+    const uint32_t *idx;   // i_mode of each nonzero, fiber order
+    const float *vals;     // values, fiber order
+    const uint32_t *perm;  // caller position of each nonzero, fiber order
+    const uint32_t *fptr;  // [nfibs + 1]
+    const uint32_t *coords[kMaxOrder];  // [order - 1][nfibs], modes in order without `mode`
 };
 
 namespace {
@@ -203,13 +217,13 @@ struct MttkrpPlan {
     size_t part_bytes;
 };
 
-bool plan_mttkrp(const pasta_coo *X, uint32_t rank, KernelShape s, MttkrpPlan &p)
+bool plan_mttkrp(uint64_t nnz, uint32_t rank, KernelShape s, MttkrpPlan &p)
 {
     p.shape = s;
     const uint32_t G = 64u / (uint32_t)s.lanes;
     p.sub = kSub;
     p.chunk = (uint64_t)p.sub * G;
-    const uint64_t nch = (X->nnz + p.chunk - 1) / p.chunk;
+    const uint64_t nch = (nnz + p.chunk - 1) / p.chunk;
     if (nch > 0x7FFFFFFFull) return false;
     p.nchunks = (uint32_t)nch;
     p.ldp = s.strided ? rank : (rank + 3u) / 4u * 4u;
@@ -220,7 +234,7 @@ bool plan_mttkrp(const pasta_coo *X, uint32_t rank, KernelShape s, MttkrpPlan &p
 }
 
 // Worst case over kernel shapes for a rank: the contiguous shape has the most chunks.
-size_t mttkrp_ws_bound(const pasta_coo *X, uint32_t rank, pasta_dtype dt)
+size_t mttkrp_ws_bound(uint64_t nnz, uint32_t rank, pasta_dtype dt)
 {
     const uint32_t vec = dt == PASTA_F32 ? 4 : 8;
     KernelShape shapes[2] = {{(int)vec, (int)next_pow2(std::max<uint32_t>(1, (rank + vec - 1) / vec)), false},
@@ -229,7 +243,7 @@ size_t mttkrp_ws_bound(const pasta_coo *X, uint32_t rank, pasta_dtype dt)
     for (auto &s : shapes) {
         if (s.lanes > 16 && !s.strided) continue;
         MttkrpPlan p;
-        if (plan_mttkrp(X, rank, s, p)) best = std::max(best, p.part_bytes);
+        if (plan_mttkrp(nnz, rank, s, p)) best = std::max(best, p.part_bytes);
     }
     return best;
 }
@@ -260,7 +274,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     KernelShape s;
     if (!choose_shape(dt, rank, ldf, ldo, fl, nf, out, s)) return PASTA_EUNSUPPORTED;
     MttkrpPlan p;
-    if (!plan_mttkrp(X, rank, s, p)) return PASTA_EUNSUPPORTED;
+    if (!plan_mttkrp(X->nnz, rank, s, p)) return PASTA_EUNSUPPORTED;
     if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
         return PASTA_EWORKSPACE;
     const auto &md = X->mode[mode];
@@ -298,6 +312,63 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     HIPCHK(launch_fixup(md.rowptr, md.sinds[mode], X->nnz, (uint32_t)X->dims[mode], l.part, p.ldp, blk, p.nchunks, out,
                         ldo, rank, p.chunk, alpha, s, st));
     return PASTA_OK;
+}
+
+// Workspace of a fiber layout: two ping-pong SoA sets for the sort (N index
+// arrays, the values, the permutation), the fiber ids, fptr, coordinates and
+// the head flags and their scan.
+struct FiberLayout {
+    size_t set[2][kMaxOrder + 2];
+    size_t fid, fptr, coords[kMaxOrder], head, excl, nfibs, hist, scanpart, total;
+    uint32_t ntiles;
+};
+
+bool make_fiber_layout(uint32_t N, uint64_t nnz, FiberLayout &L)
+{
+    size_t off = 0;
+    const size_t m4 = (size_t)nnz * 4;
+    for (int s = 0; s < 2; ++s)
+        for (uint32_t a = 0; a < N + 2; ++a) {
+            L.set[s][a] = off;
+            if (!checked_add(off, m4)) return false;
+        }
+    L.fid = off;
+    if (!checked_add(off, m4)) return false;
+    L.fptr = off;
+    if (!checked_add(off, m4 + 4)) return false;
+    for (uint32_t q = 0; q + 1 < N; ++q) {
+        L.coords[q] = off;
+        if (!checked_add(off, m4)) return false;
+    }
+    L.head = off;
+    if (!checked_add(off, m4)) return false;
+    L.excl = off;
+    if (!checked_add(off, m4)) return false;
+    L.nfibs = off;
+    checked_add(off, 4);
+    L.ntiles = (uint32_t)std::max<uint64_t>(1, (nnz + kSortTile - 1) / kSortTile);
+    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    L.hist = off;
+    if (!checked_add(off, hist_n * 4)) return false;
+    L.scanpart = off;
+    if (!checked_add(off, (std::max(scan_partials_count(hist_n), scan_partials_count(nnz)) + 1) * 4)) return false;
+    L.total = off;
+    return true;
+}
+
+// Partial slots of a TTV call: two per chunk, then the level-one fixup sums.
+struct TtvPlan {
+    uint32_t nchunks;
+    size_t blk_offset, part_bytes;
+};
+
+TtvPlan plan_ttv(uint64_t nnz)
+{
+    TtvPlan p;
+    p.nchunks = (uint32_t)((nnz + kTtvChunk - 1) / kTtvChunk);
+    p.blk_offset = align_up((size_t)2 * p.nchunks * sizeof(float));
+    p.part_bytes = p.blk_offset + align_up((size_t)((p.nchunks + 63) / 64) * sizeof(float));
+    return p;
 }
 
 }  // namespace
@@ -476,7 +547,7 @@ pasta_status pasta_mttkrp_workspace_bytes(const pasta_coo *X, uint32_t mode, uin
     if (!X || !bytes || mode >= X->order || rank == 0) return PASTA_EINVAL;
     if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
     if (rank > 256) return PASTA_EUNSUPPORTED;
-    *bytes = mttkrp_ws_bound(X, rank, dtype);
+    *bytes = mttkrp_ws_bound(X->nnz, rank, dtype);
     return PASTA_OK;
 }
 
@@ -596,7 +667,7 @@ pasta_status pasta_cp_grad_workspace_bytes(const pasta_coo *X, uint32_t rank, pa
 {
     if (!X || !bytes || rank == 0) return PASTA_EINVAL;
     if (rank > 256) return PASTA_EUNSUPPORTED;
-    const size_t part = mttkrp_ws_bound(X, rank, dtype);
+    const size_t part = mttkrp_ws_bound(X->nnz, rank, dtype);
     // one fp64 loss partial per chunk of mode 0 (no chunk is shorter than kSub nonzeros)
     const size_t nlp = (size_t)((X->nnz + kSub - 1) / kSub) + 1;
     *bytes = align_up(part) + align_up(nlp * sizeof(double));
@@ -618,7 +689,7 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
     pasta_cp_grad_workspace_bytes(X, rank, dtype, &need);
     if (!d_work || work_bytes < need || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t part = align_up(mttkrp_ws_bound(X, rank, dtype));
+    const size_t part = align_up(mttkrp_ws_bound(X->nnz, rank, dtype));
     double *lp = reinterpret_cast<double *>(static_cast<char *>(d_work) + part);
     for (uint32_t n = 0; n < X->order; ++n) {
         const bool want_loss = d_loss && n == 0;
@@ -637,7 +708,7 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
             KernelShape sh;
             choose_shape(dtype, rank, ldf, ldg, fl, X->order, d_grads[0], sh);
             MttkrpPlan p;
-            plan_mttkrp(X, rank, sh, p);
+            plan_mttkrp(X->nnz, rank, sh, p);
             HIPCHK(launch_sum_f64(lp, p.nchunks, d_loss, st));
         }
     }
@@ -668,7 +739,7 @@ AlsLayout als_layout(const pasta_coo *X, uint32_t R)
     }
     size_t off = 0;
     L.mttkrp = off;
-    off += align_up(mttkrp_ws_bound(X, R, PASTA_F32));
+    off += align_up(mttkrp_ws_bound(X->nnz, R, PASTA_F32));
     L.M = off;
     off += align_up((size_t)maxI * R * sizeof(float));
     L.grams = off;
@@ -771,6 +842,246 @@ pasta_status pasta_adam_step(float *d_param, const float *d_grad, float *d_m, fl
         return PASTA_EINVAL;
     HIPCHK(launch_adam(d_param, d_grad, d_m, d_v, d_shadow_bf16, count, lr, beta1, beta2, eps, step,
                        static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_fibers_workspace_bytes(const pasta_coo *X, uint32_t mode, size_t *bytes)
+{
+    if (!X || !bytes || mode >= X->order) return PASTA_EINVAL;
+    FiberLayout L;
+    if (!make_fiber_layout(X->order, X->nnz, L)) return PASTA_EUNSUPPORTED;
+    *bytes = L.total;
+    return PASTA_OK;
+}
+
+pasta_status pasta_fibers_create(const pasta_coo *X, uint32_t mode, void *d_workspace, size_t workspace_bytes,
+                                 void *stream, pasta_fibers **out)
+{
+    if (!out) return PASTA_EINVAL;
+    *out = nullptr;
+    if (!X || mode >= X->order) return PASTA_EINVAL;
+    FiberLayout L;
+    if (!make_fiber_layout(X->order, X->nnz, L)) return PASTA_EUNSUPPORTED;
+    if (!d_workspace || workspace_bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
+        return PASTA_EWORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_workspace);
+    auto at = [&](size_t off) { return reinterpret_cast<uint32_t *>(base + off); };
+    const uint32_t N = X->order;
+    const uint64_t nnz = X->nnz;
+    uint32_t other[kMaxOrder], no = 0;
+    for (uint32_t k = 0; k < N; ++k)
+        if (k != mode) other[no++] = k;
+
+    // the sorted arrays: N index arrays, values (as bits), permutation
+    struct Soa {
+        const uint32_t *ind[kMaxOrder];
+        const uint32_t *val, *perm;
+    };
+    const auto &md = X->mode[mode];
+    Soa cur;
+    for (uint32_t k = 0; k < N; ++k) cur.ind[k] = md.sinds[k];
+    cur.val = reinterpret_cast<const uint32_t *>(md.svals);
+    cur.perm = md.perm;
+    auto set_of = [&](int s, uint32_t *ind[kMaxOrder], uint32_t *&val, uint32_t *&perm) {
+        for (uint32_t k = 0; k < N; ++k) ind[k] = at(L.set[s][k]);
+        val = at(L.set[s][N]);
+        perm = at(L.set[s][N + 1]);
+    };
+    uint32_t host_nfibs = 0;
+    if (nnz > 0) {
+        uint32_t *hist = at(L.hist), *scanpart = at(L.scanpart);
+        const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+        // Fiber order: lexicographic in the other modes (in mode order), then
+        // i_mode, then caller position. Mode `mode`'s order is sorted by
+        // (i_mode, position) among nonzeros that agree elsewhere, so stable LSD
+        // sorts by the other modes, the highest mode first, finish it.
+        int parity = 0;
+        bool moved = false;
+        for (int qi = (int)no - 1; qi >= 0; --qi) {
+            const uint32_t k = other[qi];
+            const int passes = (key_bits(X->dims[k]) + kRadixBits - 1) / kRadixBits;
+            for (int ps = 0; ps < passes; ++ps) {
+                uint32_t *dind[kMaxOrder], *dval, *dperm;
+                set_of(parity, dind, dval, dperm);
+                SortPayload pl{};
+                int cnt = 0;
+                pl.in[cnt] = cur.perm;
+                pl.out[cnt++] = dperm;
+                for (uint32_t kk = 0; kk < N; ++kk)
+                    if (kk != k) {
+                        pl.in[cnt] = cur.ind[kk];
+                        pl.out[cnt++] = dind[kk];
+                    }
+                pl.in[cnt] = cur.val;
+                pl.out[cnt++] = dval;
+                pl.count = cnt;
+                HIPCHK(launch_radix_hist(cur.ind[k], nnz, ps * kRadixBits, hist, L.ntiles, st));
+                HIPCHK(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
+                HIPCHK(launch_radix_scatter(cur.ind[k], nnz, ps * kRadixBits, hist, L.ntiles, dind[k], pl, st));
+                for (uint32_t kk = 0; kk < N; ++kk) cur.ind[kk] = dind[kk];
+                cur.val = dval;
+                cur.perm = dperm;
+                parity ^= 1;
+                moved = true;
+            }
+        }
+        if (!moved) {  // every other mode has size 1: the mode order is the fiber order
+            uint32_t *dind[kMaxOrder], *dval, *dperm;
+            set_of(0, dind, dval, dperm);
+            SortPayload pl{};
+            int cnt = 0;
+            pl.in[cnt] = cur.perm;
+            pl.out[cnt++] = dperm;
+            for (uint32_t kk = 0; kk < N; ++kk)
+                if (kk != mode) {
+                    pl.in[cnt] = cur.ind[kk];
+                    pl.out[cnt++] = dind[kk];
+                }
+            pl.in[cnt] = cur.val;
+            pl.out[cnt++] = dval;
+            pl.count = cnt;
+            HIPCHK(launch_copy_payload(cur.ind[mode], nnz, dind[mode], pl, st));
+            for (uint32_t kk = 0; kk < N; ++kk) cur.ind[kk] = dind[kk];
+            cur.val = dval;
+            cur.perm = dperm;
+        }
+        FiberInds fi{};
+        FiberCoords fc{};
+        for (uint32_t q = 0; q < no; ++q) {
+            fi.p[q] = cur.ind[other[q]];
+            fc.p[q] = at(L.coords[q]);
+        }
+        fi.count = no;
+        HIPCHK(launch_fiber_heads(fi, nnz, at(L.head), st));
+        HIPCHK(launch_exclusive_scan(at(L.head), at(L.excl), nnz, scanpart, st));
+        HIPCHK(launch_fiber_compact(fi, nnz, at(L.head), at(L.excl), at(L.fid), at(L.fptr), fc, at(L.nfibs), st));
+        HIPCHK(hipMemcpyAsync(&host_nfibs, at(L.nfibs), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    } else {
+        HIPCHK(launch_fill_u32(at(L.fptr), 0u, 1, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    pasta_fibers *F = new (std::nothrow) pasta_fibers();
+    if (!F) return PASTA_EINVAL;
+    F->order = N;
+    F->mode = mode;
+    F->nnz = nnz;
+    F->nfibs = host_nfibs;
+    F->dim = X->dims[mode];
+    F->fid = at(L.fid);
+    F->idx = cur.ind[mode];
+    F->vals = reinterpret_cast<const float *>(cur.val);
+    F->perm = cur.perm;
+    F->fptr = at(L.fptr);
+    for (uint32_t q = 0; q < no; ++q) F->coords[q] = at(L.coords[q]);
+    *out = F;
+    return PASTA_OK;
+}
+
+pasta_status pasta_fibers_destroy(pasta_fibers *F)
+{
+    delete F;
+    return PASTA_OK;
+}
+
+pasta_status pasta_fibers_info(const pasta_fibers *F, uint32_t *mode, uint64_t *nfibs)
+{
+    if (!F) return PASTA_EINVAL;
+    if (mode) *mode = F->mode;
+    if (nfibs) *nfibs = F->nfibs;
+    return PASTA_OK;
+}
+
+pasta_status pasta_fibers_view(const pasta_fibers *F, const uint32_t **d_fptr, const uint32_t **d_coords,
+                               const uint32_t **d_perm, const uint32_t **d_fid)
+{
+    if (!F) return PASTA_EINVAL;
+    if (d_fptr) *d_fptr = F->fptr;
+    if (d_coords)
+        for (uint32_t q = 0; q + 1 < F->order; ++q) d_coords[q] = F->coords[q];
+    if (d_perm) *d_perm = F->perm;
+    if (d_fid) *d_fid = F->fid;
+    return PASTA_OK;
+}
+
+pasta_status pasta_ttm_workspace_bytes(const pasta_fibers *F, uint32_t rank, pasta_dtype dtype, size_t *bytes)
+{
+    if (!F || !bytes || rank == 0) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > (uint32_t)PASTA_MAX_RANK) return PASTA_EUNSUPPORTED;
+    *bytes = mttkrp_ws_bound(F->nnz, rank, dtype);
+    return PASTA_OK;
+}
+
+pasta_status pasta_ttm(const pasta_fibers *F, const void *d_U, pasta_dtype dtype, uint32_t rank, uint32_t ldu,
+                       float *d_out, uint32_t ldo, void *d_work, size_t work_bytes, void *stream)
+{
+    if (!F || rank == 0 || ldu < rank || ldo < rank) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > (uint32_t)PASTA_MAX_RANK) return PASTA_EUNSUPPORTED;
+    if (F->nnz == 0) return PASTA_OK;
+    if (!d_U || !d_out) return PASTA_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    KernelShape s;
+    if (!choose_shape(dtype, rank, ldu, ldo, &d_U, 1, d_out, s)) return PASTA_EUNSUPPORTED;
+    MttkrpPlan p;
+    if (!plan_mttkrp(F->nnz, rank, s, p)) return PASTA_EUNSUPPORTED;
+    if (!d_work || work_bytes < p.part_bytes || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
+    // Alg. 5 as an order-2 segmented product: the fiber id is the output row,
+    // i_mode selects the row of U.
+    MttkrpLaunch l{};
+    l.row = F->fid;
+    l.idx[0] = F->idx;
+    l.fac[0] = d_U;
+    l.vals = F->vals;
+    l.out = d_out;
+    l.part = static_cast<float *>(d_work);
+    l.nnz = F->nnz;
+    l.ldf = ldu;
+    l.ldo = ldo;
+    l.ldp = p.ldp;
+    l.rank = rank;
+    l.sub = p.sub;
+    l.nchunks = p.nchunks;
+    l.alpha = 1.0f;
+    hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+    g_ev_start = g_ev_stop = nullptr;
+    if (e0) HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(launch_mttkrp(2, l, dtype == PASTA_BF16, s, false, st));
+    if (e1) HIPCHK(hipEventRecord(e1, st));
+    float *blk = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.blk_offset);
+    HIPCHK(launch_fixup(F->fptr, F->fid, F->nnz, (uint32_t)F->nfibs, l.part, p.ldp, blk, p.nchunks, d_out, ldo, rank,
+                        p.chunk, 1.0f, s, st));
+    return PASTA_OK;
+}
+
+pasta_status pasta_ttv_workspace_bytes(const pasta_fibers *F, size_t *bytes)
+{
+    if (!F || !bytes) return PASTA_EINVAL;
+    *bytes = plan_ttv(F->nnz).part_bytes;
+    return PASTA_OK;
+}
+
+pasta_status pasta_ttv(const pasta_fibers *F, const float *d_v, float *d_out, void *d_work, size_t work_bytes,
+                       void *stream)
+{
+    if (!F) return PASTA_EINVAL;
+    if (F->nnz == 0) return PASTA_OK;
+    if (!d_v || !d_out) return PASTA_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TtvPlan p = plan_ttv(F->nnz);
+    if (!d_work || work_bytes < p.part_bytes || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
+    float *part = static_cast<float *>(d_work);
+    hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
+    g_ev_start = g_ev_stop = nullptr;
+    if (e0) HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(launch_ttv(F->fid, F->idx, F->vals, d_v, d_out, part, F->nnz, p.nchunks, st));
+    if (e1) HIPCHK(hipEventRecord(e1, st));
+    // fibers crossing chunk edges: the generic one-element-per-lane fixup
+    const KernelShape s{4, 64, true};
+    float *blk = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.blk_offset);
+    HIPCHK(launch_fixup(F->fptr, F->fid, F->nnz, (uint32_t)F->nfibs, part, 1u, blk, p.nchunks, d_out, 1u, 1u,
+                        kTtvChunk, 1.0f, s, st));
     return PASTA_OK;
 }
 

@@ -1,0 +1,39 @@
+// Launch interfaces of the fiber kernels (fibers.hip): the mode-n fiber
+// pre-processing of Algs. 4 and 5 and the TTV kernel. Every pointer is device
+// memory.
+#pragma once
+
+#include "common.h"
+
+namespace pasta {
+
+// The other modes' index arrays of a fiber-ordered stream (count = order - 1).
+struct FiberInds {
+    const uint32_t *p[kMaxOrder];
+    uint32_t count;
+};
+struct FiberCoords {
+    uint32_t *p[kMaxOrder];
+};
+
+// head[p] = 1 where nonzero p starts a fiber (p = 0, or some other-mode index
+// differs from nonzero p - 1), else 0.
+hipError_t launch_fiber_heads(const FiberInds &in, uint64_t nnz, uint32_t *head, hipStream_t st);
+// From the heads and their exclusive scan: fid[p] (fiber of nonzero p),
+// fptr[f] (first nonzero of fiber f; fptr[nfibs] = nnz), coords[q][f] (the
+// fiber's fixed indices) and *nfibs.
+hipError_t launch_fiber_compact(const FiberInds &in, uint64_t nnz, const uint32_t *head, const uint32_t *excl,
+                                uint32_t *fid, uint32_t *fptr, const FiberCoords &coords, uint32_t *nfibs,
+                                hipStream_t st);
+
+// TTV: out[f] = sum over the nonzeros p of fiber f of vals[p] * v[idx[p]].
+// One wave per chunk of kTtvChunk nonzeros, walked in tiles of kTtvTile (four
+// per lane); fibers crossing a chunk edge leave partials in part[2c] (the
+// chunk's first fiber) and part[2c + 1] (its last) for launch_fixup.
+constexpr uint32_t kTtvTile = 256;
+constexpr uint32_t kTtvTiles = 4;
+constexpr uint64_t kTtvChunk = (uint64_t)kTtvTile * kTtvTiles;
+hipError_t launch_ttv(const uint32_t *fid, const uint32_t *idx, const float *vals, const float *v, float *out,
+                      float *part, uint64_t nnz, uint32_t nchunks, hipStream_t st);
+
+}  // namespace pasta

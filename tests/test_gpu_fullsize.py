@@ -98,3 +98,69 @@ def test_all_ones_marginals_full_size(full):
         marg = np.bincount(coo.inds[n], weights=coo.vals.astype(np.float64), minlength=coo.dims[n])
         assert rel(got, np.repeat(marg[:, None], spec.rank, axis=1)) <= 1e-6
         assert np.all(got == got[:, :1])  # every column of a row is the same number
+
+
+def _sub_oracle(coo, rows, fn, operand, n):
+    """The oracle on the sub-tensor made of the given nonzeros only (whole fibers)."""
+    return fn(coo.dims, coo.inds[:, rows], coo.vals[rows], operand, n)[2]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_fibers_ttv_ttm_full_size(full, n):
+    """Mode-n fibers of the full tensor: the order is fixed by its keys (other modes in
+    order, then i_n, then caller position), fptr and coordinates follow from it; TTV and
+    TTM (R = 32, fp32 and bf16) on sampled fibers (the longest, fibers crossing chunk
+    edges, random ones) against the oracle, and TTV with a ones vector against the
+    per-fiber value sums on every fiber."""
+    spec, coo, X = full
+    from paper_1902_03317_amd import api
+    N, M = coo.order, coo.nnz
+    F = api.Fibers(X, n)
+    gfptr, gcoords, gperm, gfid = F.view()
+    p = gperm.cpu().numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(np.bincount(p, minlength=M), np.ones(M, np.int64))
+    other = [k for k in range(N) if k != n]
+    cols = [coo.inds[k][p] for k in other + [n]] + [p]
+    less = np.zeros(M - 1, bool)
+    equal = np.ones(M - 1, bool)
+    for c in cols:
+        less |= equal & (c[:-1] < c[1:])
+        equal &= c[:-1] == c[1:]
+    assert less.all()
+    new = np.ones(M, bool)
+    new[1:] = np.any([c[1:] != c[:-1] for c in cols[:N - 1]], axis=0)
+    fptr = np.append(np.flatnonzero(new), M)
+    del cols, less, equal, new
+    assert F.nfibs == fptr.size - 1
+    assert np.array_equal(gfptr.cpu().numpy().view(np.uint32), fptr)
+    for q, k in enumerate(other):
+        assert np.array_equal(gcoords[q].cpu().numpy().view(np.uint32), coo.inds[k][p[fptr[:-1]]])
+    lens = np.diff(fptr)
+    assert np.array_equal(gfid.cpu().numpy().view(np.uint32), np.repeat(np.arange(F.nfibs, dtype=np.uint32), lens))
+
+    # every fiber: TTV with a ones vector is the fiber's value sum
+    ones = torch.ones(coo.dims[n], device=DEV)
+    got1 = api.ttv(F, ones).cpu().numpy().astype(np.float64)
+    sums = np.add.reduceat(coo.vals[p].astype(np.float64), fptr[:-1])
+    assert rel(got1, sums) <= 1e-6
+
+    U = synth.make_factors(spec)[n]
+    rng = np.random.default_rng(40 + n)
+    v = U[:, 0].copy()
+    gotv = api.ttv(F, torch.from_numpy(v).to(DEV)).cpu().numpy().astype(np.float64)
+    got32 = api.ttm(F, torch.from_numpy(U).to(DEV)).cpu().numpy().astype(np.float64)
+    got16 = api.ttm(F, torch.from_numpy(U).to(DEV).to(torch.bfloat16)).cpu().numpy().astype(np.float64)
+    picks = {int(np.argmax(lens))} | set(int(f) for f in rng.choice(F.nfibs, 12, replace=False))
+    for C in (1024, 2048):  # TTV chunk; TTM chunk at R = 32 fp32
+        cross = np.flatnonzero((fptr[:-1] // C) != ((fptr[1:] - 1) // C))
+        picks |= set(int(f) for f in rng.choice(cross, min(8, cross.size), replace=False))
+    picks = sorted(picks)
+    rows = np.concatenate([p[fptr[f]:fptr[f + 1]] for f in picks])
+    want_v = _sub_oracle(coo, rows, oracle.ttv, v.astype(np.float64), n)
+    want_m = _sub_oracle(coo, rows, oracle.ttm, U.astype(np.float64), n)
+    want_b = _sub_oracle(coo, rows, oracle.ttm, oracle.bf16_round(U).astype(np.float64), n)
+    assert want_m.shape[0] == len(picks)
+    assert rel(gotv[picks], want_v) <= 1e-5
+    for i, f in enumerate(picks):
+        assert rel(got32[f], want_m[i]) <= 1e-5, f"ttm fiber {f} ({lens[f]} nonzeros)"
+        assert rel(got16[f], want_b[i]) <= 1e-5, f"ttm bf16 fiber {f} ({lens[f]} nonzeros)"
