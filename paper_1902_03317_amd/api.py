@@ -63,6 +63,7 @@ class Coo:
                                    self.workspace.data_ptr(), self.workspace.numel(), _stream(stream),
                                    ctypes.byref(h)), "pasta_coo_create")
         self._h = h
+        self._destroy = lib.pasta_coo_destroy  # still reachable while the interpreter shuts down
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -71,7 +72,7 @@ class Coo:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib.pasta_coo_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
@@ -278,6 +279,7 @@ class Fibers:
         check(lib.pasta_fibers_create(X.handle, self.mode, self.workspace.data_ptr(), self.workspace.numel(),
                                       _stream(stream), ctypes.byref(h)), "pasta_fibers_create")
         self._h = h
+        self._destroy = lib.pasta_fibers_destroy
         nf = ctypes.c_uint64()
         check(lib.pasta_fibers_info(h, None, ctypes.byref(nf)), "pasta_fibers_info")
         self.nfibs = int(nf.value)
@@ -289,7 +291,7 @@ class Fibers:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib.pasta_fibers_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def _view(self, ptr: int, count: int, dtype) -> torch.Tensor:
