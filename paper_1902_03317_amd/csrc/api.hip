@@ -32,6 +32,8 @@ struct pasta_fibers {
     uint64_t nnz, nfibs, dim;
     const uint32_t *fid;   // fiber of each nonzero, fiber order
     const uint32_t *idx;   // i_mode of each nonzero, fiber order
+    const uint32_t *hot;   // the same indices relabelled by decreasing count (TTV gathers)
+    const uint32_t *old_of_new;  // [dim] the index a relabelled index stands for
     const float *vals;     // values, fiber order
     const uint32_t *perm;  // caller position of each nonzero, fiber order
     const uint32_t *fptr;  // [nfibs + 1]
@@ -320,10 +322,11 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
 struct FiberLayout {
     size_t set[2][kMaxOrder + 2];
     size_t fid, fptr, coords[kMaxOrder], head, excl, nfibs, hist, scanpart, total;
-    uint32_t ntiles;
+    size_t hot, old_of_new, new_of_old, rkey[2], rperm[2];  // relabelling of the mode's indices
+    uint32_t ntiles, ntiles_dim;
 };
 
-bool make_fiber_layout(uint32_t N, uint64_t nnz, FiberLayout &L)
+bool make_fiber_layout(uint32_t N, uint64_t nnz, uint64_t dim, FiberLayout &L)
 {
     size_t off = 0;
     const size_t m4 = (size_t)nnz * 4;
@@ -346,8 +349,22 @@ bool make_fiber_layout(uint32_t N, uint64_t nnz, FiberLayout &L)
     if (!checked_add(off, m4)) return false;
     L.nfibs = off;
     checked_add(off, 4);
+    L.hot = off;
+    if (!checked_add(off, m4)) return false;
+    const size_t d4 = (size_t)dim * 4;
+    L.old_of_new = off;
+    if (!checked_add(off, d4)) return false;
+    L.new_of_old = off;
+    if (!checked_add(off, d4)) return false;
+    for (int s = 0; s < 2; ++s) {
+        L.rkey[s] = off;
+        if (!checked_add(off, d4)) return false;
+        L.rperm[s] = off;
+        if (!checked_add(off, d4)) return false;
+    }
     L.ntiles = (uint32_t)std::max<uint64_t>(1, (nnz + kSortTile - 1) / kSortTile);
-    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    L.ntiles_dim = (uint32_t)std::max<uint64_t>(1, (dim + kSortTile - 1) / kSortTile);
+    const uint64_t hist_n = (uint64_t)kRadix * std::max(L.ntiles, L.ntiles_dim);
     L.hist = off;
     if (!checked_add(off, hist_n * 4)) return false;
     L.scanpart = off;
@@ -356,18 +373,20 @@ bool make_fiber_layout(uint32_t N, uint64_t nnz, FiberLayout &L)
     return true;
 }
 
-// Partial slots of a TTV call: two per chunk, then the level-one fixup sums.
+// Scratch of a TTV call: two partial slots per chunk, the level-one fixup
+// sums, then the vector in relabelled index order.
 struct TtvPlan {
     uint32_t nchunks;
-    size_t blk_offset, part_bytes;
+    size_t blk_offset, vhot_offset, part_bytes;
 };
 
-TtvPlan plan_ttv(uint64_t nnz)
+TtvPlan plan_ttv(uint64_t nnz, uint64_t dim)
 {
     TtvPlan p;
     p.nchunks = (uint32_t)((nnz + kTtvChunk - 1) / kTtvChunk);
     p.blk_offset = align_up((size_t)2 * p.nchunks * sizeof(float));
-    p.part_bytes = p.blk_offset + align_up((size_t)((p.nchunks + 63) / 64) * sizeof(float));
+    p.vhot_offset = p.blk_offset + align_up((size_t)((p.nchunks + 63) / 64) * sizeof(float));
+    p.part_bytes = p.vhot_offset + align_up((size_t)dim * sizeof(float));
     return p;
 }
 
@@ -849,7 +868,7 @@ pasta_status pasta_fibers_workspace_bytes(const pasta_coo *X, uint32_t mode, siz
 {
     if (!X || !bytes || mode >= X->order) return PASTA_EINVAL;
     FiberLayout L;
-    if (!make_fiber_layout(X->order, X->nnz, L)) return PASTA_EUNSUPPORTED;
+    if (!make_fiber_layout(X->order, X->nnz, X->dims[mode], L)) return PASTA_EUNSUPPORTED;
     *bytes = L.total;
     return PASTA_OK;
 }
@@ -861,7 +880,7 @@ pasta_status pasta_fibers_create(const pasta_coo *X, uint32_t mode, void *d_work
     *out = nullptr;
     if (!X || mode >= X->order) return PASTA_EINVAL;
     FiberLayout L;
-    if (!make_fiber_layout(X->order, X->nnz, L)) return PASTA_EUNSUPPORTED;
+    if (!make_fiber_layout(X->order, X->nnz, X->dims[mode], L)) return PASTA_EUNSUPPORTED;
     if (!d_workspace || workspace_bytes < L.total || ((uintptr_t)d_workspace % kAlign) != 0)
         return PASTA_EWORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -956,6 +975,29 @@ pasta_status pasta_fibers_create(const pasta_coo *X, uint32_t mode, void *d_work
         HIPCHK(launch_fiber_heads(fi, nnz, at(L.head), st));
         HIPCHK(launch_exclusive_scan(at(L.head), at(L.excl), nnz, scanpart, st));
         HIPCHK(launch_fiber_compact(fi, nnz, at(L.head), at(L.excl), at(L.fid), at(L.fptr), fc, at(L.nfibs), st));
+        // Relabel i_mode by decreasing count (ties by index): the entries of v that
+        // a TTV gathers most often then share cache lines. Same products, same
+        // order of summation, so the results are unchanged bit for bit.
+        const uint32_t dim = (uint32_t)X->dims[mode];
+        const uint64_t hist_d = (uint64_t)kRadix * L.ntiles_dim;
+        HIPCHK(launch_count_keys(md.rowptr, dim, nnz, at(L.rkey[0]), st));
+        const int rpasses = (key_bits(nnz + 1) + kRadixBits - 1) / kRadixBits;
+        const uint32_t *kin = at(L.rkey[0]);
+        const uint32_t *pin = nullptr;  // identity
+        for (int ps = 0; ps < rpasses; ++ps) {
+            const int d = (ps + 1) & 1;
+            SortPayload pl{};
+            pl.in[0] = pin;
+            pl.out[0] = ps == rpasses - 1 ? at(L.old_of_new) : at(L.rperm[d]);
+            pl.count = 1;
+            HIPCHK(launch_radix_hist(kin, dim, ps * kRadixBits, hist, L.ntiles_dim, st));
+            HIPCHK(launch_exclusive_scan(hist, hist, hist_d, scanpart, st));
+            HIPCHK(launch_radix_scatter(kin, dim, ps * kRadixBits, hist, L.ntiles_dim, at(L.rkey[d]), pl, st));
+            kin = at(L.rkey[d]);
+            pin = pl.out[0];
+        }
+        HIPCHK(launch_invert_perm(at(L.old_of_new), dim, at(L.new_of_old), st));
+        HIPCHK(launch_gather_u32(at(L.new_of_old), cur.ind[mode], nnz, at(L.hot), st));
         HIPCHK(hipMemcpyAsync(&host_nfibs, at(L.nfibs), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     } else {
         HIPCHK(launch_fill_u32(at(L.fptr), 0u, 1, st));
@@ -970,6 +1012,8 @@ pasta_status pasta_fibers_create(const pasta_coo *X, uint32_t mode, void *d_work
     F->dim = X->dims[mode];
     F->fid = at(L.fid);
     F->idx = cur.ind[mode];
+    F->hot = at(L.hot);
+    F->old_of_new = at(L.old_of_new);
     F->vals = reinterpret_cast<const float *>(cur.val);
     F->perm = cur.perm;
     F->fptr = at(L.fptr);
@@ -1051,14 +1095,14 @@ pasta_status pasta_ttm(const pasta_fibers *F, const void *d_U, pasta_dtype dtype
     if (e1) HIPCHK(hipEventRecord(e1, st));
     float *blk = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.blk_offset);
     HIPCHK(launch_fixup(F->fptr, F->fid, F->nnz, (uint32_t)F->nfibs, l.part, p.ldp, blk, p.nchunks, d_out, ldo, rank,
-                        p.chunk, 1.0f, s, st));
+                        p.chunk, 1.0f, s, st, true));
     return PASTA_OK;
 }
 
 pasta_status pasta_ttv_workspace_bytes(const pasta_fibers *F, size_t *bytes)
 {
     if (!F || !bytes) return PASTA_EINVAL;
-    *bytes = plan_ttv(F->nnz).part_bytes;
+    *bytes = plan_ttv(F->nnz, F->dim).part_bytes;
     return PASTA_OK;
 }
 
@@ -1069,19 +1113,21 @@ pasta_status pasta_ttv(const pasta_fibers *F, const float *d_v, float *d_out, vo
     if (F->nnz == 0) return PASTA_OK;
     if (!d_v || !d_out) return PASTA_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const TtvPlan p = plan_ttv(F->nnz);
+    const TtvPlan p = plan_ttv(F->nnz, F->dim);
     if (!d_work || work_bytes < p.part_bytes || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;
     float *part = static_cast<float *>(d_work);
+    float *vhot = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.vhot_offset);
+    HIPCHK(launch_gather_f32(d_v, F->old_of_new, F->dim, vhot, st));  // v in relabelled order
     hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
     g_ev_start = g_ev_stop = nullptr;
     if (e0) HIPCHK(hipEventRecord(e0, st));
-    HIPCHK(launch_ttv(F->fid, F->idx, F->vals, d_v, d_out, part, F->nnz, p.nchunks, st));
+    HIPCHK(launch_ttv(F->fid, F->hot, F->vals, vhot, d_out, part, F->nnz, p.nchunks, st));
     if (e1) HIPCHK(hipEventRecord(e1, st));
     // fibers crossing chunk edges: the generic one-element-per-lane fixup
     const KernelShape s{4, 64, true};
     float *blk = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.blk_offset);
     HIPCHK(launch_fixup(F->fptr, F->fid, F->nnz, (uint32_t)F->nfibs, part, 1u, blk, p.nchunks, d_out, 1u, 1u,
-                        kTtvChunk, 1.0f, s, st));
+                        kTtvChunk, 1.0f, s, st, true));
     return PASTA_OK;
 }
 

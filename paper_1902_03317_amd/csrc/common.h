@@ -226,10 +226,12 @@ hipError_t launch_permute(uint32_t order, uint32_t mode, uint64_t n, const uint3
 hipError_t launch_rowptr(const uint32_t *sorted_rows, uint64_t n, uint32_t nrows, uint32_t *rowptr,
                          hipStream_t st);
 // Rows crossing chunk edges (and empty rows) after the main MTTKRP kernel; blk
-// holds ceil(nchunks / 64) level-one partial rows (stride ldp).
+// holds ceil(nchunks / 64) level-one partial rows (stride ldp). by_chunk:
+// find the split rows from the chunk edges (streams with no empty rows).
 hipError_t launch_fixup(const uint32_t *rowptr, const uint32_t *row, uint64_t nnz, uint32_t nrows,
                         const float *part, uint32_t ldp, float *blk, uint64_t nchunks, float *out, uint32_t ldo,
-                        uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st);
+                        uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st,
+                        bool by_chunk = false);
 hipError_t launch_sum_f64(const double *part, uint32_t n, double *out, hipStream_t st);
 hipError_t launch_cast_bf16(const float *src, uint16_t *dst, uint64_t n, hipStream_t st);
 hipError_t launch_zero_rows(float *out, uint32_t nrows, uint32_t ldo, uint32_t rank, hipStream_t st);

@@ -26,6 +26,15 @@ hipError_t launch_fiber_compact(const FiberInds &in, uint64_t nnz, const uint32_
                                 uint32_t *fid, uint32_t *fptr, const FiberCoords &coords, uint32_t *nfibs,
                                 hipStream_t st);
 
+// Frequency relabelling of a mode's index space (so that the entries of v a
+// TTV gathers most often share cache lines): keys[i] = nnz - count[i] from a
+// row-offset array, so an ascending stable sort lists indices by decreasing
+// count; inv[perm[j]] = j; out[p] = table[idx[p]] (u32 and f32).
+hipError_t launch_count_keys(const uint32_t *rowptr, uint32_t n, uint64_t nnz, uint32_t *keys, hipStream_t st);
+hipError_t launch_invert_perm(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t st);
+hipError_t launch_gather_u32(const uint32_t *table, const uint32_t *idx, uint64_t n, uint32_t *out, hipStream_t st);
+hipError_t launch_gather_f32(const float *table, const uint32_t *idx, uint64_t n, float *out, hipStream_t st);
+
 // TTV: out[f] = sum over the nonzeros p of fiber f of vals[p] * v[idx[p]].
 // One wave per chunk of kTtvChunk nonzeros, walked in tiles of kTtvTile (four
 // per lane); fibers crossing a chunk edge leave partials in part[2c] (the

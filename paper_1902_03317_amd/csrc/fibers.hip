@@ -52,6 +52,28 @@ __global__ __launch_bounds__(256) void fiber_compact_kernel(const FiberInds in, 
     }
 }
 
+__global__ __launch_bounds__(256) void count_keys_kernel(const uint32_t *__restrict__ rowptr, uint32_t n,
+                                                         uint64_t nnz, uint32_t *__restrict__ keys)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        keys[i] = (uint32_t)(nnz - (uint64_t)(rowptr[i + 1] - rowptr[i]));
+}
+
+__global__ __launch_bounds__(256) void invert_perm_kernel(const uint32_t *__restrict__ perm, uint32_t n,
+                                                          uint32_t *__restrict__ inv)
+{
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (uint64_t)gridDim.x * blockDim.x)
+        inv[perm[j]] = (uint32_t)j;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(const T *__restrict__ table, const uint32_t *__restrict__ idx,
+                                                     uint64_t n, T *__restrict__ out)
+{
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x)
+        out[p] = table[idx[p]];
+}
+
 // ---------------------------------------------------------------------------
 // TTV over the fiber-ordered stream. Lane l of the wave takes nonzeros
 // 4l .. 4l+3 of a 256-nonzero tile (one 16-byte load per stream, so a tile is
@@ -88,30 +110,43 @@ __global__ __launch_bounds__(256) void ttv_seg_kernel(const uint32_t *__restrict
 
     uint32_t carry_row = kNoRow;  // open fiber at the end of the previous tile (wave-uniform)
     float carry = 0.0f;
-    for (uint64_t base = c0; base < c1; base += kTtvTile) {
-        const uint64_t q = base + 4u * (uint64_t)lane;
-        const int nv = q < c1 ? (c1 - q < 4 ? (int)(c1 - q) : 4) : 0;
+    struct Tile {
         uint32_t f[4], ix[4];
         float x[4];
-        if (nv == 4) {
+        int nv;
+    };
+    auto load_tile = [&](uint64_t base, Tile &T) {
+        const uint64_t q = base + 4u * (uint64_t)lane;
+        T.nv = q < c1 ? (c1 - q < 4 ? (int)(c1 - q) : 4) : 0;
+        if (T.nv == 4) {
             const uint4 tf = *reinterpret_cast<const uint4 *>(fid + q);
             const uint4 ti = *reinterpret_cast<const uint4 *>(idx + q);
             const float4 tx = *reinterpret_cast<const float4 *>(vals + q);
-            f[0] = tf.x; f[1] = tf.y; f[2] = tf.z; f[3] = tf.w;
-            ix[0] = ti.x; ix[1] = ti.y; ix[2] = ti.z; ix[3] = ti.w;
-            x[0] = tx.x; x[1] = tx.y; x[2] = tx.z; x[3] = tx.w;
+            T.f[0] = tf.x; T.f[1] = tf.y; T.f[2] = tf.z; T.f[3] = tf.w;
+            T.ix[0] = ti.x; T.ix[1] = ti.y; T.ix[2] = ti.z; T.ix[3] = ti.w;
+            T.x[0] = tx.x; T.x[1] = tx.y; T.x[2] = tx.z; T.x[3] = tx.w;
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const bool on = e < nv;
-                f[e] = on ? fid[q + e] : kNoRow;
-                ix[e] = on ? idx[q + e] : 0u;
-                x[e] = on ? vals[q + e] : 0.0f;
+                const bool on = e < T.nv;
+                T.f[e] = on ? fid[q + e] : kNoRow;
+                T.ix[e] = on ? idx[q + e] : 0u;
+                T.x[e] = on ? vals[q + e] : 0.0f;
             }
         }
+    };
+    // One tile: the gathers for T go out first, then the next tile's loads
+    // (so their latency overlaps this tile's work), then the reduction.
+    auto tile = [&](uint64_t base, Tile &T, Tile &next) {
+        float w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[e] = v[T.ix[e]];
+        __builtin_amdgcn_sched_barrier(0);
+        if (base + kTtvTile < c1) load_tile(base + kTtvTile, next);
+        const int nv = T.nv;
         float p[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) p[e] = x[e] * v[ix[e]];
+        for (int e = 0; e < 4; ++e) p[e] = T.x[e] * w[e];
 
         // runs inside the lane
         uint32_t cur = kNoRow, hrow = kNoRow;
@@ -120,7 +155,7 @@ __global__ __launch_bounds__(256) void ttv_seg_kernel(const uint32_t *__restrict
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             if (e < nv) {
-                if (f[e] != cur) {
+                if (T.f[e] != cur) {
                     if (cur != kNoRow) {
                         if (!multi) {
                             head = acc;
@@ -130,7 +165,7 @@ __global__ __launch_bounds__(256) void ttv_seg_kernel(const uint32_t *__restrict
                             emit(cur, acc);  // a whole fiber inside the lane
                         }
                     }
-                    cur = f[e];
+                    cur = T.f[e];
                     acc = 0.0f;
                 }
                 acc += p[e];
@@ -162,6 +197,18 @@ __global__ __launch_bounds__(256) void ttv_seg_kernel(const uint32_t *__restrict
         if (cur != kNoRow && lane < lastlane && !next_cont) emit(cur, c);
         carry_row = (uint32_t)__shfl((int)cur, lastlane);
         carry = __shfl(c, lastlane);
+    };
+    // tiles with the two buffers' roles alternating (no register copies of loads in flight)
+    static_assert(kTtvTiles % 2 == 0, "tiles come in pairs");
+    Tile ta, tb;
+    load_tile(c0, ta);
+#pragma unroll
+    for (uint32_t t = 0; t < kTtvTiles; t += 2) {
+        const uint64_t base = c0 + (uint64_t)t * kTtvTile;
+        if (base >= c1) break;
+        tile(base, ta, tb);
+        if (base + kTtvTile >= c1) break;
+        tile(base + kTtvTile, tb, ta);
     }
     if (lane == 0 && carry_row != kNoRow) emit(carry_row, carry);
 }
@@ -181,6 +228,34 @@ hipError_t launch_fiber_compact(const FiberInds &in, uint64_t nnz, const uint32_
 {
     if (nnz == 0) return hipSuccess;
     fiber_compact_kernel<<<grid_of(nnz, 256), 256, 0, st>>>(in, nnz, head, excl, fid, fptr, coords, nfibs);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_keys(const uint32_t *rowptr, uint32_t n, uint64_t nnz, uint32_t *keys, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    count_keys_kernel<<<grid_of(n, 256), 256, 0, st>>>(rowptr, n, nnz, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_perm(const uint32_t *perm, uint32_t n, uint32_t *inv, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    invert_perm_kernel<<<grid_of(n, 256), 256, 0, st>>>(perm, n, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_u32(const uint32_t *table, const uint32_t *idx, uint64_t n, uint32_t *out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    gather_kernel<uint32_t><<<grid_of(n, 256), 256, 0, st>>>(table, idx, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_f32(const float *table, const uint32_t *idx, uint64_t n, float *out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    gather_kernel<float><<<grid_of(n, 256), 256, 0, st>>>(table, idx, n, out);
     return hipGetLastError();
 }
 

@@ -442,11 +442,19 @@ __global__ __launch_bounds__(256) void fixup_blocks_kernel(const uint32_t *__res
     if (g == 0 && S::active(j, rank)) store_slice<VEC, STRIDED>(blk + b * ldp, j, rank, acc, 1.0f);
 }
 
+//
+// Chunk-driven form (for streams whose rows are never empty, such as fibers,
+// where rows far outnumber chunks): candidate rows come from the chunk edges
+// instead of from a scan over all rows. Chunk c proposes the row that holds
+// its last nonzero when that row continues into chunk c + 1 and starts inside
+// chunk c, so each split row is proposed exactly once.
 template <int VEC, int L, bool STRIDED>
 __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__ rowptr, uint32_t nrows,
                                                     const float *__restrict__ part, uint32_t ldp,
                                                     const float *__restrict__ blk, float *__restrict__ out,
-                                                    uint32_t ldo, uint32_t rank, uint64_t chunk, float alpha)
+                                                    uint32_t ldo, uint32_t rank, uint64_t chunk, float alpha,
+                                                    const uint32_t *__restrict__ row, uint64_t nnz, uint64_t nchunks,
+                                                    bool by_chunk)
 {
     constexpr int G = kWave / L;
     using S = Slice<float, VEC, STRIDED>;
@@ -456,15 +464,23 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     auto slot_of = [&](uint64_t ca, uint64_t q) { return q == 0 ? 2 * ca + 1 : 2 * (ca + q); };
-    for (uint64_t t = wid; t * 64 < nrows; t += waves) {
-        const uint64_t r = t * 64 + lane;
+    const uint64_t items = by_chunk ? nchunks : nrows;
+    for (uint64_t t = wid; t * 64 < items; t += waves) {
+        uint64_t r = t * 64 + lane;
         uint32_t a = 0, b = 0;
-        if (r < nrows) {
+        bool live = r < items;
+        if (by_chunk && live) {
+            const uint64_t c = r, c1 = (c + 1) * chunk;
+            live = c1 < nnz && row[c1] == row[c1 - 1];
+            r = live ? row[c1 - 1] : 0;
+            if (live) live = rowptr[r] >= c * chunk;  // the row starts in this chunk
+        }
+        if (live) {
             a = rowptr[r];
             b = rowptr[r + 1];
         }
-        const bool empty = r < nrows && a == b;
-        const bool split = r < nrows && a < b && (a / chunk) != ((b - 1) / chunk);
+        const bool empty = live && a == b;
+        const bool split = live && a < b && (a / chunk) != ((b - 1) / chunk);
         const uint64_t cnt = split ? (b - 1) / chunk - a / chunk + 1 : 0;
         if (empty) {  // each lane clears its own row
             float *o = out + r * (uint64_t)ldo;
@@ -479,6 +495,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
             // inactive yields 0, and the row's lane may sit in a group without a row.
             const int src = m ? __ffsll((long long)m) - 1 : 0;
             const uint32_t aa = __shfl(a, src), bb = __shfl(b, src);
+            const uint64_t rr = (uint32_t)__shfl((int)(uint32_t)r, src);
             if (m && bb > aa) {
                 const uint64_t ca = aa / chunk, n = (bb - 1) / chunk - ca + 1;
                 float acc[VEC];
@@ -492,7 +509,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) acc[e] += v[e];
                     }
-                    store_slice<VEC, STRIDED>(out + (t * 64 + src) * (uint64_t)ldo, j, rank, acc, alpha);
+                    store_slice<VEC, STRIDED>(out + rr * (uint64_t)ldo, j, rank, acc, alpha);
                 }
             }
             for (int i = 0; i < G && light; ++i) light &= light - 1;
@@ -503,6 +520,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
             const int src = __ffsll((long long)heavy) - 1;
             heavy &= heavy - 1;
             const uint32_t aa = __shfl(a, src), bb = __shfl(b, src);
+            const uint64_t rr = (uint32_t)__shfl((int)(uint32_t)r, src);
             const uint64_t ca = aa / chunk, cb = (bb - 1) / chunk;
             // items: the tail of chunk ca, the heads of chunks ca+1..cb, where the
             // level-one blocks lying wholly in ca+1..cb-1 (chunks of this row only)
@@ -545,16 +563,16 @@ __global__ __launch_bounds__(256) void fixup_kernel(const uint32_t *__restrict__
             for (int off = L; off < 64; off <<= 1)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) acc[e] += __shfl_xor(acc[e], off);
-            if (g == 0 && lane_on) store_slice<VEC, STRIDED>(out + (t * 64 + src) * (uint64_t)ldo, j, rank, acc, alpha);
+            if (g == 0 && lane_on) store_slice<VEC, STRIDED>(out + rr * (uint64_t)ldo, j, rank, acc, alpha);
         }
     }
 }
 
 hipError_t launch_fixup(const uint32_t *rowptr, const uint32_t *row, uint64_t nnz, uint32_t nrows,
                         const float *part, uint32_t ldp, float *blk, uint64_t nchunks, float *out, uint32_t ldo,
-                        uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st)
+                        uint32_t rank, uint64_t chunk, float alpha, KernelShape s, hipStream_t st, bool by_chunk)
 {
-    const uint64_t tiles = ((uint64_t)nrows + 63) / 64;
+    const uint64_t tiles = ((by_chunk ? nchunks : (uint64_t)nrows) + 63) / 64;
     const unsigned grid = grid_for(tiles, 4, 4096);
     const uint64_t nblk = (nchunks + kFixupBlock - 1) / kFixupBlock;
     const unsigned bgrid = (unsigned)((nblk + 3) / 4);
@@ -562,9 +580,14 @@ hipError_t launch_fixup(const uint32_t *rowptr, const uint32_t *row, uint64_t nn
     do {                                                                                                         \
         if (nblk > 0 && nnz > 0)                                                                                 \
             fixup_blocks_kernel<V, LL, STR><<<bgrid, 256, 0, st>>>(row, nnz, part, ldp, blk, nblk, rank, chunk);  \
-        fixup_kernel<V, LL, STR><<<grid, 256, 0, st>>>(rowptr, nrows, part, ldp, blk, out, ldo, rank, chunk, alpha); \
+        fixup_kernel<V, LL, STR><<<grid, 256, 0, st>>>(rowptr, nrows, part, ldp, blk, out, ldo, rank, chunk, alpha, \
+                                                       row, nnz, nchunks, by_chunk);                                \
     } while (0)
-    if (s.strided) {
+    if (s.strided && rank == 1) {
+        // one scalar row per lane, 64 rows per wave: a strided slice with one
+        // lane and one element covers element 0, the whole row when R = 1
+        PASTA_FIXUP(1, 1, true);
+    } else if (s.strided) {
         PASTA_FIXUP(4, 64, true);
     } else {
         // partial rows are fp32: a bf16 shape (8 per lane) maps to 4 per lane on twice the lanes
