@@ -21,7 +21,12 @@ Section 5.2 Alg. 6 of the suite):
     contiguous run (the pre-processing step of Algs. 4 and 5);
   * ``ttm``: Y = X x_n U (Section 4.4, eq. ttm, U of shape I_n x R), kept
     semi-sparse as one dense R-vector per fiber (Alg. 5);
-  * ``ttv``: Y = X x_n v (Section 4.3), one value per fiber (Alg. 4).
+  * ``ttv``: Y = X x_n v (Section 4.3), one value per fiber (Alg. 4);
+  * ``tew_eq`` / ``ts``: element-wise operations of two tensors with the same
+    nonzero pattern, and tensor-scalar operations (Section 4.1-4.2, Algs. 1
+    and 3);
+  * ``tew``: the general element-wise operation of two tensors of the same
+    order, by the sorted merge of Alg. 2.
 """
 from __future__ import annotations
 
@@ -65,6 +70,9 @@ def lib():
         L.oracle_cp_loss.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         L.oracle_cp_loss.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
+        L.oracle_tew_merge.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, P, P, ctypes.c_uint64, P, P,
+                                       ctypes.c_uint64, P, P]
+        L.oracle_tew_merge.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -301,3 +309,61 @@ def ttv(dims, inds, vals, v, mode: int):
         raise ValueError("v must be a vector")
     fptr, coords, Y = ttm(dims, inds, vals, v[:, None], mode)
     return fptr, coords, Y[:, 0]
+
+
+_EW = {"add": lambda a, b: a + b, "sub": lambda a, b: a - b, "mul": lambda a, b: a * b, "div": lambda a, b: a / b}
+
+
+def tew_eq(op: str, x, y) -> np.ndarray:
+    """Element-wise operation of two tensors with the same nonzero pattern (Alg. 1 and its
+    siblings, Section 4.1): z[m] = x[m] op y[m], FP64 (IEEE: x / 0 is +-inf or nan)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if x.shape != y.shape:
+        raise ValueError("same pattern: the value arrays must match")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return _EW[op](x, y)
+
+
+def ts(op: str, x, s: float) -> np.ndarray:
+    """Tensor-scalar operation on every nonzero (Section 4.2, Alg. 3): y[m] = x[m] op s, FP64."""
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return _EW[op](x, np.float64(s))
+
+
+def lex_order(inds) -> np.ndarray:
+    """Stable lexicographic order of the nonzeros, mode 0 most significant (Section 5.2)."""
+    inds = np.asarray(inds)
+    return np.lexsort([inds[k] for k in reversed(range(inds.shape[0]))]).astype(np.uint32)
+
+
+def tew(op: str, dims_x, inds_x, vals_x, dims_y, inds_y, vals_y):
+    """General element-wise operation of two sparse tensors of the same order (Alg. 2):
+    the output shape is the element-wise maximum of the two shapes; both inputs are
+    sorted lexicographically and merged, every coordinate held by either input
+    appearing once in lexicographic order. add: x + y (or the one present); sub:
+    x - y (or x, or -y); mul: x * y where both hold the coordinate. Repeated
+    coordinates within one input count as their sum. FP64.
+    Returns (dims_z, inds_z [N, nnz_z] uint32, vals_z [nnz_z])."""
+    code = {"add": 0, "sub": 1, "mul": 2}[op]
+    inds_x = np.asarray(inds_x, dtype=np.uint32)
+    inds_y = np.asarray(inds_y, dtype=np.uint32)
+    N = inds_x.shape[0]
+    if inds_y.shape[0] != N or len(dims_x) != N or len(dims_y) != N:
+        raise ValueError("the two tensors need the same order")
+    dims_z = tuple(max(int(a), int(b)) for a, b in zip(dims_x, dims_y))
+    ox, oy = lex_order(inds_x), lex_order(inds_y)
+    sx = np.ascontiguousarray(inds_x[:, ox])
+    sy = np.ascontiguousarray(inds_y[:, oy])
+    vx = np.ascontiguousarray(np.asarray(vals_x, np.float64)[ox])
+    vy = np.ascontiguousarray(np.asarray(vals_y, np.float64)[oy])
+    Mx, My = sx.shape[1], sy.shape[1]
+    cap = Mx + My
+    iz = np.empty((N, max(cap, 1)), dtype=np.uint32)
+    vz = np.empty(max(cap, 1), dtype=np.float64)
+    nz = lib().oracle_tew_merge(N, code, Mx, sx.ctypes.data, vx.ctypes.data, My, sy.ctypes.data, vy.ctypes.data,
+                                max(cap, 1), iz.ctypes.data, vz.ctypes.data)
+    if nz < 0:
+        raise ValueError("oracle: bad argument")
+    return dims_z, np.ascontiguousarray(iz[:, :nz]), vz[:nz].copy()

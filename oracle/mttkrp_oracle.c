@@ -188,3 +188,61 @@ int oracle_cp_loss(int N, const uint64_t *dims, uint64_t M, const uint32_t *inds
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/*
+ * General element-wise operation of two sparse tensors of the same order
+ * (Section 5.2, Alg. 2 and its text): both inputs arrive sorted
+ * lexicographically (mode 0 most significant); two cursors walk them and
+ * every coordinate present in either input is appended once, in order:
+ *   op 0 (add): x + y, x alone, y alone;
+ *   op 1 (sub): x - y, x alone, -y alone;
+ *   op 2 (mul): x * y only where both hold the coordinate.
+ * Repeated coordinates inside one input are summed first (the tensor is the
+ * sum of its entries). inds_*: SoA [k*M + m]; the output holds at most
+ * Mx + My entries (SoA stride cap). Returns the output count, or -1.
+ */
+static int lex_cmp(int N, const uint32_t *a, uint64_t sa, uint64_t ia, const uint32_t *b, uint64_t sb, uint64_t ib)
+{
+    for (int k = 0; k < N; ++k) {
+        const uint32_t x = a[k * sa + ia], y = b[k * sb + ib];
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+
+int64_t oracle_tew_merge(int N, int op, uint64_t Mx, const uint32_t *ix, const double *vx, uint64_t My,
+                         const uint32_t *iy, const double *vy, uint64_t cap, uint32_t *iz, double *vz)
+{
+    if (N < 1 || N > 16 || op < 0 || op > 2 || cap < Mx + My) return -1;
+    uint64_t a = 0, b = 0, nz = 0;
+    while (a < Mx || b < My) {
+        int c;
+        if (a >= Mx) c = 1;
+        else if (b >= My) c = -1;
+        else c = lex_cmp(N, ix, Mx, a, iy, My, b);
+        const uint32_t *src = c <= 0 ? ix : iy;
+        const uint64_t ss = c <= 0 ? Mx : My, is = c <= 0 ? a : b;
+        double sx = 0.0, sy = 0.0;
+        int hx = 0, hy = 0;
+        if (c <= 0) {  /* the run of this coordinate in X */
+            const uint64_t a0 = a;
+            while (a < Mx && lex_cmp(N, ix, Mx, a, ix, Mx, a0) == 0) sx += vx[a++];
+            hx = 1;
+        }
+        if (c >= 0) {  /* and in Y */
+            const uint64_t b0 = b;
+            while (b < My && lex_cmp(N, iy, My, b, iy, My, b0) == 0) sy += vy[b++];
+            hy = 1;
+        }
+        double z;
+        if (op == 0) z = sx + sy;
+        else if (op == 1) z = sx - sy;
+        else {
+            if (!(hx && hy)) continue;
+            z = sx * sy;
+        }
+        for (int k = 0; k < N; ++k) iz[k * cap + nz] = src[k * ss + is];
+        vz[nz++] = z;
+    }
+    return (int64_t)nz;
+}
