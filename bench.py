@@ -418,6 +418,37 @@ def main():
                           "bytes_alg_per_mode": algb, "nfibs": nfibs}
         line["ttm"]["rank"] = R
         line["fibers_preprocess_ms"] = [round(t, 3) for t in pre_f]
+
+        # same-pattern element-wise op, tensor-scalar op (pure streams) and the general
+        # element-wise op of the tensor with itself (the paper's setup: sort + merge)
+        def timed(fn, reps):
+            fn()
+            ts_ = []
+            for _ in range(reps):
+                a0, a1 = hip.event(), hip.event()
+                hip.record(a0, s_ptr)
+                fn()
+                hip.record(a1, s_ptr)
+                ts_.append(hip.ms(a0, a1))
+            return sorted(ts_)[len(ts_) // 2]
+
+        y2 = (vals_d * 0.5 + 1.0).contiguous()
+        zt = torch.empty_like(vals_d)
+        t_eq = timed(lambda: api.tew_eq("add", vals_d, y2, out=zt), 10)
+        t_ts = timed(lambda: api.ts("mul", vals_d, 0.5, out=zt), 10)
+        ws_tew = torch.empty(api.tew_workspace_bytes(N, M, M), dtype=torch.uint8, device=dev)
+        res = {}
+
+        def general():
+            res["z"] = api.tew("add", coo.dims, inds_d, vals_d, coo.dims, inds_d, vals_d, workspace=ws_tew)
+        t_tew = timed(general, 3)
+        for name, t, nb in (("tew_eq", t_eq, 12 * M), ("ts", t_ts, 8 * M)):
+            line[name] = {"op": "add" if name == "tew_eq" else "mul", "ms": round(t, 4),
+                          "gb_s": round(nb / (t * 1e-3) / 1e9, 1),
+                          "hbm_frac": round(nb / (t * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4), "bytes": nb}
+        line["tew"] = {"op": "add", "inputs": "the tensor with itself", "ms": round(t_tew, 3),
+                       "gnnz_s": round(2 * M / (t_tew * 1e-3) / 1e9, 3), "nnz_out": int(res["z"][2].numel())}
+        del ws_tew, res, y2, zt
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cb, (m, inds_s, vals_s, outs_o) = cpu_baseline(coo, U)

@@ -9,8 +9,9 @@
  *
  * for every row i of mode n (rows without nonzeros are zero), plus the
  * sampled CP model and its residual-weighted MTTKRP gradient (CP
- * decomposition, Section 3.1.1), a CP-ALS sweep, and the fiber-based sparse
- * TTM and TTV of Sections 4.3-4.4 (Algs. 4 and 5).
+ * decomposition, Section 3.1.1), a CP-ALS sweep, the fiber-based sparse
+ * TTM and TTV of Sections 4.3-4.4 (Algs. 4 and 5), and the element-wise
+ * (TEW) and tensor-scalar (TS) operations of Sections 4.1-4.2 (Algs. 1-3).
  *
  * Conventions shared by every entry point
  *   - Coordinates are 0-based (the COO example of Section 5.1); indices are
@@ -25,7 +26,7 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     All work is enqueued on it and the call returns without waiting,
  *     except pasta_coo_create, which waits once for its index check, and
- *     pasta_fibers_create, which waits once to read the fiber count.
+ *     pasta_fibers_create and pasta_tew, which wait once to read a count.
  *   - Argument errors are reported synchronously through the return value
  *     and nothing is enqueued; the library never aborts or throws.
  *   - Calls that share a handle may run concurrently only if they do not
@@ -51,6 +52,9 @@ typedef enum {
 } pasta_status;
 
 typedef enum { PASTA_F32 = 0, PASTA_BF16 = 1 } pasta_dtype;
+
+/* Element-wise / tensor-scalar operator (Sections 4.1-4.2). */
+typedef enum { PASTA_ADD = 0, PASTA_SUB = 1, PASTA_MUL = 2, PASTA_DIV = 3 } pasta_ewop;
 
 /* Opaque host-side handle of a preprocessed COO tensor. It points into the
  * caller's workspace and the caller's original index/value arrays, which
@@ -258,6 +262,43 @@ pasta_status pasta_ttm(const pasta_fibers *F, const void *d_U, pasta_dtype dtype
  * Deterministic. */
 pasta_status pasta_ttv_workspace_bytes(const pasta_fibers *F, size_t *bytes);
 pasta_status pasta_ttv(const pasta_fibers *F, const float *d_v, float *d_out, void *d_work, size_t work_bytes,
+                       void *stream);
+
+/* ---- Element-wise and tensor-scalar operations ------------------------- */
+/* Same-pattern element-wise operation (Section 4.1; Alg. 1 for addition):
+ * X and Y hold the same coordinates in the same order, so only the values
+ * are combined: d_z[m] = d_x[m] op d_y[m] for m < nnz (fp32, IEEE
+ * semantics: correctly rounded, x / 0 gives inf or nan). Z's coordinates
+ * are X's: the caller shares (or copies) the index arrays. d_z may alias
+ * d_x or d_y. */
+pasta_status pasta_tew_eq(pasta_ewop op, uint64_t nnz, const float *d_x, const float *d_y, float *d_z, void *stream);
+
+/* Tensor-scalar operation on every nonzero (Section 4.2; Alg. 3 for
+ * multiplication): d_y[m] = d_x[m] op s; the pattern is unchanged (implicit
+ * zeros stay zero). d_y may alias d_x. */
+pasta_status pasta_ts(pasta_ewop op, uint64_t nnz, const float *d_x, float s, float *d_y, void *stream);
+
+/* General element-wise operation of two sparse tensors of the same order
+ * with any patterns and shapes (Section 4.1; Alg. 2): the output shape is
+ * the element-wise maximum of the two shapes; the output lists, in
+ * lexicographic order (mode 0 most significant), every coordinate that
+ *   PASTA_ADD: either input holds, with x + y (or the one present);
+ *   PASTA_SUB: either input holds, with x - y (or x, or -y);
+ *   PASTA_MUL: both inputs hold, with x * y;
+ * PASTA_DIV is not offered (an implicit zero divisor). Repeated coordinates
+ * inside one input count as their sum (in that input's order).
+ *   d_inds_*  host arrays of `order` device pointers (1 <= order <= 8);
+ *   dims_z    host array filled with the output shape;
+ *   d_inds_z, d_vals_z  capacity nnz_x + nnz_y each; *nnz_z receives the
+ *             output count (host).
+ *   d_work    >= pasta_tew_workspace_bytes, 256-byte aligned.
+ * Waits for the stream once. PASTA_ERANGE if a coordinate is outside its
+ * input's shape (the output is then undefined). */
+pasta_status pasta_tew_workspace_bytes(uint32_t order, uint64_t nnz_x, uint64_t nnz_y, size_t *bytes);
+pasta_status pasta_tew(uint32_t order, pasta_ewop op, const uint64_t *dims_x, uint64_t nnz_x,
+                       const uint32_t *const *d_inds_x, const float *d_vals_x, const uint64_t *dims_y, uint64_t nnz_y,
+                       const uint32_t *const *d_inds_y, const float *d_vals_y, uint64_t *dims_z,
+                       uint32_t *const *d_inds_z, float *d_vals_z, uint64_t *nnz_z, void *d_work, size_t work_bytes,
                        void *stream);
 
 /* Text of a status code (static storage). */

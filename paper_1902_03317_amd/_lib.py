@@ -27,6 +27,7 @@ F32 = ctypes.c_float
 
 PASTA_F32 = 0
 PASTA_BF16 = 1
+EWOP = {"add": 0, "sub": 1, "mul": 2, "div": 3}
 STATUS = {0: "PASTA_OK", 1: "PASTA_EINVAL", 2: "PASTA_ERANGE", 3: "PASTA_EUNSUPPORTED", 4: "PASTA_EWORKSPACE",
           5: "PASTA_EHIP"}
 
@@ -60,6 +61,10 @@ SIGNATURES = {
     "pasta_ttm": [P, P, ctypes.c_int, U32, U32, P, U32, P, SZ, P],
     "pasta_ttv_workspace_bytes": [P, ctypes.POINTER(SZ)],
     "pasta_ttv": [P, P, P, P, SZ, P],
+    "pasta_tew_eq": [ctypes.c_int, U64, P, P, P, P],
+    "pasta_ts": [ctypes.c_int, U64, P, F32, P, P],
+    "pasta_tew_workspace_bytes": [U32, U64, U64, ctypes.POINTER(SZ)],
+    "pasta_tew": [U32, ctypes.c_int, P, U64, P, P, P, U64, P, P, P, P, P, ctypes.POINTER(U64), P, SZ, P],
 }
 
 for _name, _args in SIGNATURES.items():

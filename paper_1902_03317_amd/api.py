@@ -360,3 +360,69 @@ def ttv(F: Fibers, v: torch.Tensor, out: Optional[torch.Tensor] = None, workspac
     check(lib.pasta_ttv(F.handle, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
           "pasta_ttv")
     return out
+
+
+def _values(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+def tew_eq(op: str, x: torch.Tensor, y: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Same-pattern element-wise operation (Alg. 1): out = x op y on the value arrays; op in add/sub/mul/div."""
+    _values(x, "x")
+    _values(y, "y")
+    if x.numel() != y.numel():
+        raise ValueError("same pattern: x and y need the same length")
+    out = torch.empty_like(x) if out is None else _values(out, "out")
+    check(lib.pasta_tew_eq(_lib.EWOP[op], x.numel(), x.data_ptr(), y.data_ptr(), out.data_ptr(), _stream(stream)),
+          "pasta_tew_eq")
+    return out
+
+
+def ts(op: str, x: torch.Tensor, s: float, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Tensor-scalar operation on every nonzero (Alg. 3): out = x op s; op in add/sub/mul/div."""
+    _values(x, "x")
+    out = torch.empty_like(x) if out is None else _values(out, "out")
+    check(lib.pasta_ts(_lib.EWOP[op], x.numel(), x.data_ptr(), float(s), out.data_ptr(), _stream(stream)), "pasta_ts")
+    return out
+
+
+def tew_workspace_bytes(order: int, nnz_x: int, nnz_y: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib.pasta_tew_workspace_bytes(int(order), int(nnz_x), int(nnz_y), ctypes.byref(n)),
+          "pasta_tew_workspace_bytes")
+    return n.value
+
+
+def tew(op: str, dims_x: Sequence[int], inds_x: torch.Tensor, vals_x: torch.Tensor, dims_y: Sequence[int],
+        inds_y: torch.Tensor, vals_y: torch.Tensor, workspace: Optional[torch.Tensor] = None, stream=None):
+    """General element-wise operation of two sparse tensors of the same order (Alg. 2).
+
+    inds_* are int32 CUDA tensors [N, nnz]; returns (dims_z, inds_z [N, nnz_z] int32, vals_z [nnz_z]) with the
+    output in lexicographic order; op in add/sub/mul."""
+    N = len(dims_x)
+    if len(dims_y) != N or inds_x.shape[0] != N or inds_y.shape[0] != N:
+        raise ValueError("the two tensors need the same order")
+    for t, name in ((inds_x, "inds_x"), (inds_y, "inds_y")):
+        if not t.is_cuda or t.dtype != torch.int32:
+            raise TypeError(f"{name} must be an int32 CUDA tensor")
+    _values(vals_x, "vals_x")
+    _values(vals_y, "vals_y")
+    nx, ny = int(vals_x.numel()), int(vals_y.numel())
+    ix = [inds_x[k].contiguous() for k in range(N)]
+    iy = [inds_y[k].contiguous() for k in range(N)]
+    cap = max(nx + ny, 1)
+    iz = torch.empty((N, cap), dtype=torch.int32, device=vals_x.device)
+    vz = torch.empty(cap, dtype=torch.float32, device=vals_x.device)
+    ws = workspace if workspace is not None else _scratch(tew_workspace_bytes(N, nx, ny), vals_x.device)
+    dx = (ctypes.c_uint64 * N)(*[int(d) for d in dims_x])
+    dy = (ctypes.c_uint64 * N)(*[int(d) for d in dims_y])
+    dz = (ctypes.c_uint64 * N)()
+    nz = ctypes.c_uint64()
+    check(lib.pasta_tew(N, _lib.EWOP[op], dx, nx, ptr_array([t.data_ptr() for t in ix]), vals_x.data_ptr(), dy, ny,
+                        ptr_array([t.data_ptr() for t in iy]), vals_y.data_ptr(), dz,
+                        ptr_array([iz[k].data_ptr() for k in range(N)]), vz.data_ptr(), ctypes.byref(nz),
+                        ws.data_ptr(), ws.numel(), _stream(stream)), "pasta_tew")
+    n = int(nz.value)
+    return tuple(int(d) for d in dz), iz[:, :n], vz[:n]

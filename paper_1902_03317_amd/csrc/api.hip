@@ -7,6 +7,7 @@
 
 #include "../../include/pasta.h"
 #include "common.h"
+#include "elementwise.h"
 #include "fibers.h"
 
 using namespace pasta;
@@ -388,6 +389,43 @@ TtvPlan plan_ttv(uint64_t nnz, uint64_t dim)
     p.vhot_offset = p.blk_offset + align_up((size_t)((p.nchunks + 63) / 64) * sizeof(float));
     p.part_bytes = p.vhot_offset + align_up((size_t)dim * sizeof(float));
     return p;
+}
+
+// Workspace of a general element-wise operation over nnz_x + nnz_y entries:
+// two ping-pong SoA sets (N indices, values, positions) for the sort, then
+// run heads / run ids / per-run value, position, keep flag and output slot.
+struct TewLayout {
+    size_t set[2][kMaxOrder + 2];
+    size_t head, run_of, run_val, run_pos, run_keep, out_of, flag, count, hist, scanpart, total;
+    uint32_t ntiles;
+};
+
+bool make_tew_layout(uint32_t N, uint64_t M, TewLayout &L)
+{
+    size_t off = 0;
+    const size_t m4 = (size_t)M * 4;
+    for (int s = 0; s < 2; ++s)
+        for (uint32_t a = 0; a < N + 2; ++a) {
+            L.set[s][a] = off;
+            if (!checked_add(off, m4)) return false;
+        }
+    size_t *arrs[] = {&L.head, &L.run_of, &L.run_val, &L.run_pos, &L.run_keep, &L.out_of};
+    for (size_t *a : arrs) {
+        *a = off;
+        if (!checked_add(off, m4)) return false;
+    }
+    L.flag = off;
+    checked_add(off, 4);
+    L.count = off;
+    checked_add(off, 4);
+    L.ntiles = (uint32_t)std::max<uint64_t>(1, (M + kSortTile - 1) / kSortTile);
+    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    L.hist = off;
+    if (!checked_add(off, hist_n * 4)) return false;
+    L.scanpart = off;
+    if (!checked_add(off, (std::max(scan_partials_count(hist_n), scan_partials_count(M)) + 1) * 4)) return false;
+    L.total = off;
+    return true;
 }
 
 }  // namespace
@@ -1128,6 +1166,166 @@ pasta_status pasta_ttv(const pasta_fibers *F, const float *d_v, float *d_out, vo
     float *blk = reinterpret_cast<float *>(static_cast<char *>(d_work) + p.blk_offset);
     HIPCHK(launch_fixup(F->fptr, F->fid, F->nnz, (uint32_t)F->nfibs, part, 1u, blk, p.nchunks, d_out, 1u, 1u,
                         kTtvChunk, 1.0f, s, st, true));
+    return PASTA_OK;
+}
+
+pasta_status pasta_tew_eq(pasta_ewop op, uint64_t nnz, const float *d_x, const float *d_y, float *d_z, void *stream)
+{
+    if ((int)op < PASTA_ADD || (int)op > PASTA_DIV) return PASTA_EINVAL;
+    if (nnz == 0) return PASTA_OK;
+    if (!d_x || !d_y || !d_z) return PASTA_EINVAL;
+    HIPCHK(launch_ew((int)op, d_x, d_y, 0.0f, d_z, nnz, static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_ts(pasta_ewop op, uint64_t nnz, const float *d_x, float s, float *d_y, void *stream)
+{
+    if ((int)op < PASTA_ADD || (int)op > PASTA_DIV) return PASTA_EINVAL;
+    if (nnz == 0) return PASTA_OK;
+    if (!d_x || !d_y) return PASTA_EINVAL;
+    HIPCHK(launch_ew((int)op, d_x, nullptr, s, d_y, nnz, static_cast<hipStream_t>(stream)));
+    return PASTA_OK;
+}
+
+pasta_status pasta_tew_workspace_bytes(uint32_t order, uint64_t nnz_x, uint64_t nnz_y, size_t *bytes)
+{
+    if (!bytes || order < 1) return PASTA_EINVAL;
+    if (order > (uint32_t)kMaxOrder || nnz_x + nnz_y >= (1ull << 32)) return PASTA_EUNSUPPORTED;
+    TewLayout L;
+    if (!make_tew_layout(order, nnz_x + nnz_y, L)) return PASTA_EUNSUPPORTED;
+    *bytes = L.total;
+    return PASTA_OK;
+}
+
+pasta_status pasta_tew(uint32_t order, pasta_ewop op, const uint64_t *dims_x, uint64_t nnz_x,
+                       const uint32_t *const *d_inds_x, const float *d_vals_x, const uint64_t *dims_y, uint64_t nnz_y,
+                       const uint32_t *const *d_inds_y, const float *d_vals_y, uint64_t *dims_z,
+                       uint32_t *const *d_inds_z, float *d_vals_z, uint64_t *nnz_z, void *d_work, size_t work_bytes,
+                       void *stream)
+{
+    if (!dims_x || !dims_y || !dims_z || !nnz_z || order < 1) return PASTA_EINVAL;
+    if (op == PASTA_DIV) return PASTA_EUNSUPPORTED;
+    if ((int)op < PASTA_ADD || (int)op > PASTA_MUL) return PASTA_EINVAL;
+    if (order > (uint32_t)kMaxOrder || nnz_x + nnz_y >= (1ull << 32)) return PASTA_EUNSUPPORTED;
+    for (uint32_t k = 0; k < order; ++k) {
+        if (dims_x[k] == 0 || dims_y[k] == 0) return PASTA_EINVAL;
+        if (dims_x[k] > (1ull << 31) || dims_y[k] > (1ull << 31)) return PASTA_EUNSUPPORTED;
+    }
+    const uint64_t M = nnz_x + nnz_y;
+    if (nnz_x && (!d_inds_x || !d_vals_x)) return PASTA_EINVAL;
+    if (nnz_y && (!d_inds_y || !d_vals_y)) return PASTA_EINVAL;
+    if (M && (!d_inds_z || !d_vals_z)) return PASTA_EINVAL;
+    for (uint32_t k = 0; k < order; ++k) {
+        if (nnz_x && !d_inds_x[k]) return PASTA_EINVAL;
+        if (nnz_y && !d_inds_y[k]) return PASTA_EINVAL;
+        if (M && !d_inds_z[k]) return PASTA_EINVAL;
+    }
+    TewLayout L;
+    if (!make_tew_layout(order, M, L)) return PASTA_EUNSUPPORTED;
+    if (M && (!d_work || work_bytes < L.total || ((uintptr_t)d_work % kAlign) != 0)) return PASTA_EWORKSPACE;
+    uint64_t dz[kMaxOrder];
+    for (uint32_t k = 0; k < order; ++k) dz[k] = std::max(dims_x[k], dims_y[k]);  // the unified shape
+    if (M == 0) {
+        for (uint32_t k = 0; k < order; ++k) dims_z[k] = dz[k];
+        *nnz_z = 0;
+        return PASTA_OK;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(d_work);
+    auto at = [&](size_t off) { return reinterpret_cast<uint32_t *>(base + off); };
+    const uint32_t N = order;
+    uint32_t *flag = at(L.flag);
+    HIPCHK(launch_fill_u32(flag, 0u, 1, st));
+    if (nnz_x) HIPCHK(launch_validate(d_inds_x, dims_x, N, nnz_x, flag, st));
+    if (nnz_y) HIPCHK(launch_validate(d_inds_y, dims_y, N, nnz_y, flag, st));
+    // X then Y, side by side in set 0 (index arrays 0..N-1, values N)
+    for (uint32_t k = 0; k < N; ++k) {
+        uint32_t *dst = at(L.set[0][k]);
+        if (nnz_x) HIPCHK(hipMemcpyAsync(dst, d_inds_x[k], nnz_x * 4, hipMemcpyDeviceToDevice, st));
+        if (nnz_y) HIPCHK(hipMemcpyAsync(dst + nnz_x, d_inds_y[k], nnz_y * 4, hipMemcpyDeviceToDevice, st));
+    }
+    {
+        uint32_t *dst = at(L.set[0][N]);
+        if (nnz_x) HIPCHK(hipMemcpyAsync(dst, d_vals_x, nnz_x * 4, hipMemcpyDeviceToDevice, st));
+        if (nnz_y) HIPCHK(hipMemcpyAsync(dst + nnz_x, d_vals_y, nnz_y * 4, hipMemcpyDeviceToDevice, st));
+    }
+    // Stable LSD sort into lexicographic order, mode 0 most significant (Alg. 2's
+    // sort); equal coordinates keep X's entries first, each input in its own order.
+    struct Soa {
+        const uint32_t *ind[kMaxOrder];
+        const uint32_t *val, *perm;
+    } cur;
+    for (uint32_t k = 0; k < N; ++k) cur.ind[k] = at(L.set[0][k]);
+    cur.val = at(L.set[0][N]);
+    cur.perm = nullptr;  // identity until the first pass writes it
+    int parity = 1;
+    uint32_t *hist = at(L.hist), *scanpart = at(L.scanpart);
+    const uint64_t hist_n = (uint64_t)kRadix * L.ntiles;
+    auto pass = [&](uint32_t k, int shift, bool sort) -> pasta_status {
+        uint32_t *dind[kMaxOrder];
+        for (uint32_t kk = 0; kk < N; ++kk) dind[kk] = at(L.set[parity][kk]);
+        uint32_t *dval = at(L.set[parity][N]), *dperm = at(L.set[parity][N + 1]);
+        SortPayload pl{};
+        int cnt = 0;
+        pl.in[cnt] = cur.perm;
+        pl.out[cnt++] = dperm;
+        for (uint32_t kk = 0; kk < N; ++kk)
+            if (kk != k) {
+                pl.in[cnt] = cur.ind[kk];
+                pl.out[cnt++] = dind[kk];
+            }
+        pl.in[cnt] = cur.val;
+        pl.out[cnt++] = dval;
+        pl.count = cnt;
+        if (sort) {
+            HIPCHK(launch_radix_hist(cur.ind[k], M, shift, hist, L.ntiles, st));
+            HIPCHK(launch_exclusive_scan(hist, hist, hist_n, scanpart, st));
+            HIPCHK(launch_radix_scatter(cur.ind[k], M, shift, hist, L.ntiles, dind[k], pl, st));
+        } else {
+            HIPCHK(launch_copy_payload(cur.ind[k], M, dind[k], pl, st));
+        }
+        for (uint32_t kk = 0; kk < N; ++kk) cur.ind[kk] = dind[kk];
+        cur.val = dval;
+        cur.perm = dperm;
+        parity ^= 1;
+        return PASTA_OK;
+    };
+    bool moved = false;
+    for (int k = (int)N - 1; k >= 0; --k) {
+        const int passes = (key_bits(dz[k]) + kRadixBits - 1) / kRadixBits;
+        for (int ps = 0; ps < passes; ++ps) {
+            pasta_status e = pass((uint32_t)k, ps * kRadixBits, true);
+            if (e != PASTA_OK) return e;
+            moved = true;
+        }
+    }
+    if (!moved) {  // every mode has size 1: keep the concatenation order, write the positions
+        pasta_status e = pass(0, 0, false);
+        if (e != PASTA_OK) return e;
+    }
+    // runs of equal coordinates, reduced and compacted in order
+    FiberInds fi{};
+    TewInds ti{};
+    for (uint32_t k = 0; k < N; ++k) fi.p[k] = ti.p[k] = cur.ind[k];
+    fi.count = N;
+    uint32_t *head = at(L.head), *run_of = at(L.run_of), *run_keep = at(L.run_keep), *out_of = at(L.out_of);
+    HIPCHK(launch_fiber_heads(fi, M, head, st));
+    HIPCHK(launch_exclusive_scan(head, run_of, M, scanpart, st));
+    HIPCHK(launch_fill_u32(run_keep, 0u, M, st));
+    float *run_val = reinterpret_cast<float *>(at(L.run_val));
+    HIPCHK(launch_tew_runs(head, run_of, cur.perm, reinterpret_cast<const float *>(cur.val), M, nnz_x, (int)op,
+                           run_val, at(L.run_pos), run_keep, st));
+    HIPCHK(launch_exclusive_scan(run_keep, out_of, M, scanpart, st));
+    TewOut to{};
+    for (uint32_t k = 0; k < N; ++k) to.p[k] = d_inds_z[k];
+    HIPCHK(launch_tew_emit(ti, N, at(L.run_pos), run_val, run_keep, out_of, M, to, d_vals_z, at(L.count), st));
+    uint32_t host[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&host[0], at(L.count), 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&host[1], flag, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (host[1]) return PASTA_ERANGE;
+    for (uint32_t k = 0; k < order; ++k) dims_z[k] = dz[k];
+    *nnz_z = host[0];
     return PASTA_OK;
 }
 
