@@ -146,11 +146,12 @@ def cpu_baseline(coo, U, budget_s: float = 12.0):
         m = max(m, int(budget_s / per_nnz))
     else:
         m = coo.nnz
-    reps = max(1, int(round(budget_s / (per_nnz * m))))
-    total = 0.0
-    for _ in range(reps):
+    # passes until about budget_s seconds (the small first run overstates the per-nonzero cost)
+    reps, total = 0, 0.0
+    while reps == 0 or total < budget_s:
         t, outs, inds, vals = run(m)
         total += t
+        reps += 1
     what = "the whole tensor" if m == coo.nnz else f"the first {m} of {coo.nnz} nonzeros (a uniform sample)"
     return {"value": round(reps * coo.order * m / total / 1e9, 5), "unit": "Gnnz/s", "cores": threads,
             "kind": "oracle",
