@@ -217,23 +217,45 @@ hipError_t launch_radix_hist(const uint32_t *keys, uint64_t n, int shift, uint32
 // staged in LDS: each key's place inside the tile (digit start within the
 // tile + equal digits before it) is found first, the tile is laid out in LDS
 // in that order, and then each digit's run is written to its global place as
-// one contiguous range, so global writes are coalesced. Payload arrays go
-// through LDS one at a time.
+// one contiguous range, so global writes are coalesced.
+//
+// Wave w of the block takes the contiguous quarter w of the tile and ranks its
+// keys alone (ballots per 64 keys and a wave-private running count per digit),
+// so ranking needs no block barrier; the waves' counts are then turned into
+// per-wave digit offsets, which keeps equal digits in input order (stable).
+// Payload arrays go through LDS one at a time, each one's loads issued while
+// the previous one is being written.
 __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__restrict__ keys_in, uint64_t n,
                                                             int shift, const uint32_t *__restrict__ offsets,
                                                             uint32_t ntiles, uint32_t *__restrict__ keys_out,
                                                             SortPayload pl)
 {
-    __shared__ uint32_t lstart[kRadix];         // first slot of each digit inside the tile
-    __shared__ uint32_t gstart[kRadix];         // its first place in the output
-    __shared__ uint32_t next[kRadix];           // next free slot of each digit inside the tile
-    __shared__ uint32_t wcnt[4][kRadix + 1];    // this round's count per wave (+1: idle lanes)
+    constexpr uint32_t kPer = kSortTile / kSortThreads;  // keys per lane (rounds of 64 per wave)
+    constexpr uint32_t kQuarter = kSortTile / 4;         // keys per wave
+    __shared__ uint32_t lstart[kRadix];                  // first slot of each digit inside the tile
+    __shared__ uint32_t gstart[kRadix];                  // its first place in the output
+    __shared__ uint32_t wc[4][kRadix];                   // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t lds4[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     const uint32_t tile_n = (uint32_t)(n - base < kSortTile ? n - base : kSortTile);
+    const uint32_t wbase = (uint32_t)wave * kQuarter + (uint32_t)lane;  // + 64 * r: this lane's r-th key
+
+    // keys first, then the first payload array (loads return in order)
+    uint32_t key[kPer], pv[kPer];
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t li = wbase + 64u * r;
+        key[r] = li < tile_n ? keys_in[base + li] : 0u;
+    }
+    const uint32_t *src0 = pl.count > 0 ? pl.in[0] : nullptr;
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t li = wbase + 64u * r;
+        pv[r] = li < tile_n ? (src0 ? src0[base + li] : (uint32_t)(base + li)) : 0u;
+    }
     // this tile's digit counts from the scanned histogram (digit-major, exclusive)
     {
         const uint32_t d = threadIdx.x;
@@ -243,21 +265,18 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
         const uint32_t cnt = (j < last ? offsets[j + 1] : (uint32_t)n) - g0;
         gstart[d] = g0;
         uint32_t total;
-        const uint32_t ex = block_excl_scan_u32(cnt, lds4, &total);
-        lstart[d] = ex;
-        next[d] = ex;
+        lstart[d] = block_excl_scan_u32(cnt, lds4, &total);
+        wc[0][d] = wc[1][d] = wc[2][d] = wc[3][d] = 0;
     }
-    for (uint32_t d = threadIdx.x; d < 4 * (kRadix + 1); d += 256) (&wcnt[0][0])[d] = 0;
     __syncthreads();
+
+    // rank inside the wave: equal digits before this key in the wave's quarter
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint32_t lpos[kSortItems];
+    uint32_t rk[kPer];
 #pragma unroll
-    for (uint32_t round = 0; round < kSortItems; ++round) {
-        const uint32_t li = round * kSortThreads + threadIdx.x;
-        const bool on = li < tile_n;
-        const uint32_t key = on ? keys_in[base + li] : 0u;
-        const uint32_t d = on ? ((key >> shift) & (kRadix - 1)) : kRadix;
-        // lanes of this wave holding the same digit (idle lanes share digit kRadix)
+    for (uint32_t r = 0; r < kPer; ++r) {
+        const bool on = wbase + 64u * r < tile_n;
+        const uint32_t d = on ? ((key[r] >> shift) & (kRadix - 1)) : kRadix;  // idle lanes: digit kRadix
         uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b <= kRadixBits; ++b) {
@@ -265,36 +284,55 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
             const uint64_t bal = __ballot(bit);
             peers &= bit ? bal : ~bal;
         }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        if (rank == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        lpos[round] = 0;
-        if (on) {
-            uint32_t pos = next[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            lpos[round] = pos;
-            s_key[pos] = key;
-        }
-        __syncthreads();
-        for (uint32_t dd = threadIdx.x; dd < kRadix; dd += 256) {
-            next[dd] += wcnt[0][dd] + wcnt[1][dd] + wcnt[2][dd] + wcnt[3][dd];
-            wcnt[0][dd] = wcnt[1][dd] = wcnt[2][dd] = wcnt[3][dd] = 0;
-        }
-        __syncthreads();
+        const uint32_t da = d & (kRadix - 1);                // an in-range address for idle lanes too
+        const uint32_t before = on ? wc[wave][da] : 0u;      // read by every lane before the leader writes
+        const uint32_t within = __popcll(peers & lt_mask);
+        if (on && within == 0) wc[wave][da] = before + (uint32_t)__popcll(peers);
+        rk[r] = before + within;
     }
+    __syncthreads();
+    // per-wave offsets of each digit (waves in tile order)
+    {
+        const uint32_t d = threadIdx.x;
+        uint32_t a = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t t = wc[w][d];
+            wc[w][d] = a;
+            a += t;
+        }
+    }
+    __syncthreads();
+    uint32_t lpos[kPer];
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+        lpos[r] = 0;
+        if (wbase + 64u * r < tile_n) {
+            const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+            lpos[r] = lstart[d] + wc[wave][d] + rk[r];
+            s_key[lpos[r]] = key[r];
+        }
+    }
+    __syncthreads();
     // keys, in tile order: slot i of digit d goes to gstart[d] + (i - lstart[d])
     for (uint32_t i = threadIdx.x; i < tile_n; i += kSortThreads) {
-        const uint32_t key = s_key[i];
-        const uint32_t d = (key >> shift) & (kRadix - 1);
-        keys_out[gstart[d] + (i - lstart[d])] = key;
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & (kRadix - 1);
+        keys_out[gstart[d] + (i - lstart[d])] = k;
     }
     for (int k = 0; k < pl.count; ++k) {
-        const uint32_t *src = pl.in[k];
+        uint32_t nv[kPer];
+        if (k + 1 < pl.count) {  // the next array's loads go out before this one is written
+            const uint32_t *src = pl.in[k + 1];
 #pragma unroll
-        for (uint32_t round = 0; round < kSortItems; ++round) {
-            const uint32_t li = round * kSortThreads + threadIdx.x;
-            if (li < tile_n) s_val[lpos[round]] = src ? src[base + li] : (uint32_t)(base + li);
+            for (uint32_t r = 0; r < kPer; ++r) {
+                const uint32_t li = wbase + 64u * r;
+                nv[r] = li < tile_n ? src[base + li] : 0u;
+            }
         }
+#pragma unroll
+        for (uint32_t r = 0; r < kPer; ++r)
+            if (wbase + 64u * r < tile_n) s_val[lpos[r]] = pv[r];
         __syncthreads();
         uint32_t *dst = pl.out[k];
         for (uint32_t i = threadIdx.x; i < tile_n; i += kSortThreads) {
@@ -302,6 +340,10 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
             dst[gstart[d] + (i - lstart[d])] = s_val[i];
         }
         __syncthreads();
+        if (k + 1 < pl.count) {
+#pragma unroll
+            for (uint32_t r = 0; r < kPer; ++r) pv[r] = nv[r];
+        }
     }
 }
 
