@@ -458,8 +458,9 @@ def main():
         import oracle
         Xs = X if m == coo.nnz else api.Coo(coo.dims, torch.from_numpy(inds_s.view(np.int32)).to(dev),
                                             torch.from_numpy(vals_s.astype(np.float32)).to(dev))
-        e32 = max(oracle.rel_fro(api.mttkrp(Xs, Ud, n).cpu().numpy(), outs_o[n]) for n in range(N))
-        Ub = [api.cast_bf16(u) for u in Ud]
+        U32 = [torch.from_numpy(u).to(dev) for u in U]  # the fp32 factors, whatever the timed dtype
+        e32 = max(oracle.rel_fro(api.mttkrp(Xs, U32, n).cpu().numpy(), outs_o[n]) for n in range(N))
+        Ub = [api.cast_bf16(u) for u in U32]
         e16 = max(oracle.rel_fro(api.mttkrp(Xs, Ub, n).cpu().numpy(), outs_o[n]) for n in range(N))
         line["error_vs_fp64_oracle"] = {"mttkrp_f32_max_mode_rel_fro": e32, "mttkrp_bf16_max_mode_rel_fro": e16,
                                         "sample_nnz": m}

@@ -164,3 +164,87 @@ def test_fibers_ttv_ttm_full_size(full, n):
     for i, f in enumerate(picks):
         assert rel(got32[f], want_m[i]) <= 1e-5, f"ttm fiber {f} ({lens[f]} nonzeros)"
         assert rel(got16[f], want_b[i]) <= 1e-5, f"ttm bf16 fiber {f} ({lens[f]} nonzeros)"
+
+
+# ---- the order-4 (100M nonzeros, R = 64) and order-5 (200M nonzeros, R = 64) workloads ----
+
+def _load(cfg):
+    spec = synth.CONFIGS[cfg]
+    coo = synth.load_or_make_coo(spec, CACHE)
+    return spec, coo, upload(coo)
+
+
+@pytest.fixture(scope="module")
+def order4():
+    return _load(3)
+
+
+@pytest.fixture(scope="module")
+def order5():
+    return _load(5)
+
+
+def _sampled_rows(spec, coo, X, dtype, seed, nrand=6, ncross=4):
+    """MTTKRP of every mode at full size, checked on the hottest row, rows crossing chunk
+    edges and random non-empty rows, each computed by the oracle from that row's nonzeros."""
+    from paper_1902_03317_amd import api
+    U = synth.make_factors(spec)
+    fd = factors_dev(U, dtype)
+    U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
+    rng = np.random.default_rng(seed)
+    R = spec.rank
+    lanes = max(1, R * (2 if dtype == torch.bfloat16 else 4) // 16)
+    C = 256 * (64 // lanes)
+    worst = 0.0
+    for n in range(coo.order):
+        out = api.mttkrp(X, fd, n).cpu().numpy().astype(np.float64)
+        counts = np.bincount(coo.inds[n], minlength=coo.dims[n])
+        starts = np.concatenate([[0], np.cumsum(counts)])
+        nonempty = np.flatnonzero(counts)
+        crossing = np.flatnonzero(((starts[:-1] // C) != ((starts[1:] - 1) // C)) & (counts > 0))
+        rows = {int(np.argmax(counts))} | set(int(r) for r in rng.choice(nonempty, min(nrand, nonempty.size),
+                                                                        replace=False))
+        rows |= set(int(r) for r in rng.choice(crossing, min(ncross, crossing.size), replace=False))
+        empty = np.flatnonzero(counts == 0)
+        if empty.size:
+            assert not np.any(out[empty[: 1000]])
+        for r in sorted(rows):
+            want = _row_oracle(coo, U64, n, r)
+            e = rel(out[r], want)
+            worst = max(worst, e)
+            assert e <= 1e-5, f"mode {n} row {r} ({counts[r]} nonzeros): {e:.3e}"
+        del out
+    return worst
+
+
+def test_order4_full_size_sampled_rows(order4):
+    spec, coo, X = order4
+    _sampled_rows(spec, coo, X, torch.float32, 51)
+
+
+def test_order4_full_size_all_ones_marginals(order4):
+    spec, coo, X = order4
+    from paper_1902_03317_amd import api
+    for n in range(coo.order):
+        ones = [torch.ones((d, 8), device=DEV) for d in coo.dims]
+        got = api.mttkrp(X, ones, n).cpu().numpy().astype(np.float64)
+        marg = np.bincount(coo.inds[n], weights=coo.vals.astype(np.float64), minlength=coo.dims[n])
+        assert rel(got, np.repeat(marg[:, None], 8, axis=1)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_order5_full_size_sampled_rows(order5, dtype):
+    """fp32 and bf16 factor storage; with bf16 the rows are compared with the oracle on the
+    bf16-rounded factors (fp32 accumulation error only, the fp32 bar)."""
+    spec, coo, X = order5
+    _sampled_rows(spec, coo, X, dtype, 52 if dtype == torch.float32 else 53, nrand=4, ncross=3)
+
+
+def test_order5_full_size_all_ones_marginals(order5):
+    spec, coo, X = order5
+    from paper_1902_03317_amd import api
+    for n in range(coo.order):
+        ones = [torch.ones((d, 4), device=DEV) for d in coo.dims]
+        got = api.mttkrp(X, ones, n).cpu().numpy().astype(np.float64)
+        marg = np.bincount(coo.inds[n], weights=coo.vals.astype(np.float64), minlength=coo.dims[n])
+        assert rel(got, np.repeat(marg[:, None], 4, axis=1)) <= 1e-6
