@@ -221,18 +221,23 @@ def main():
     ws_m = torch.empty(max(api.mttkrp_workspace_bytes(X, n, R, Ud[0].dtype) for n in range(N)), dtype=torch.uint8,
                        device=dev)
 
-    do_cp = not args.mttkrp_only and args.config == 2
+    do_cp = not args.mttkrp_only
+    do_extra = do_cp and args.config == 2  # CP-ALS, TTM/TTV and TEW/TS timings: headline tensor only
     if do_cp:
-        # the CP fit's tensor: same coordinates, planted rank-R values + 1% noise
-        cspec = synth.CONFIGS[4]
         sc = synth.cp_planted_scale(R, N)
-        A = [torch.from_numpy(a).to(dev) for a in synth.make_factors(cspec, rank=R, scale=sc)]
-        x = api.cp_sample(X, A)
-        rms = torch.sqrt(torch.mean(x.double() ** 2)).item()
-        noise = torch.from_numpy(synth.make_noise(cspec, coo.nnz).astype(np.float32)).to(dev)
-        xv = (x + np.float32(0.01 * rms) * noise).contiguous()
-        del noise, x
-        X4 = api.Coo(coo.dims, inds_d, xv)
+        if args.config == 2:
+            # the CP fit's tensor: same coordinates, planted rank-R values + 1% noise
+            cspec = synth.CONFIGS[4]
+            A = [torch.from_numpy(a).to(dev) for a in synth.make_factors(cspec, rank=R, scale=sc)]
+            x = api.cp_sample(X, A)
+            rms = torch.sqrt(torch.mean(x.double() ** 2)).item()
+            noise = torch.from_numpy(synth.make_noise(cspec, coo.nnz).astype(np.float32)).to(dev)
+            xv = (x + np.float32(0.01 * rms) * noise).contiguous()
+            del noise, x, A
+            X4 = api.Coo(coo.dims, inds_d, xv)
+        else:  # the gradient step on the tensor's own values (its timing does not depend on them)
+            cspec = spec
+            X4 = X
         init = synth.make_init(cspec, rank=R, scale=sc)
         m32 = [torch.from_numpy(u).to(dev) for u in init]
         m16 = [t.clone() for t in m32]
@@ -357,7 +362,7 @@ def main():
                               "bf16_speedup": round(line["breakdown_ms"]["cp_step_f32"] /
                                                     line["breakdown_ms"]["cp_step_bf16"], 3)}
         line["cp_loss_last"] = {"f32": loss_hist[-1][0], "bf16": loss_hist[-1][1]}
-    if do_cp:
+    if do_extra:
         # CP-ALS sweep (MTTKRP + normal equations + normalisation, every mode), timed apart
         Ua = [u.clone() for u in Ud] if args.factor_dtype == "f32" else [torch.from_numpy(u).to(dev) for u in U]
         lam = torch.empty(R, dtype=torch.float32, device=dev)
@@ -375,7 +380,7 @@ def main():
             hip.record(e1, s_ptr)
             ts.append(hip.ms(e0, e1))
         line["cp_als_sweep_ms"] = round(sorted(ts)[len(ts) // 2], 4)
-    if do_cp:
+    if do_extra:
         # sparse TTM (rank R, fp32 U) and TTV along every mode (Algs. 5 and 4), timed apart:
         # fiber pre-processing once per mode, then call and main-kernel times (median of 10)
         Uf = [torch.from_numpy(u).to(dev) for u in U]
@@ -464,6 +469,18 @@ def main():
         e16 = max(oracle.rel_fro(api.mttkrp(Xs, Ub, n).cpu().numpy(), outs_o[n]) for n in range(N))
         line["error_vs_fp64_oracle"] = {"mttkrp_f32_max_mode_rel_fro": e32, "mttkrp_bf16_max_mode_rel_fro": e16,
                                         "sample_nnz": m}
+        if do_cp:
+            # the CP gradient (loss + every factor's gradient) at the fit's starting point, fp32 and bf16
+            # factors, against the FP64 oracle's gradient of the same sample
+            init_s = synth.make_init(cspec, rank=R, scale=synth.cp_planted_scale(R, N))
+            I32 = [torch.from_numpy(u).to(dev) for u in init_s]
+            _, gg32 = api.cp_grad(Xs, I32)
+            _, gg16 = api.cp_grad(Xs, [api.cast_bf16(u) for u in I32])
+            _, go = oracle.cp_grad(coo.dims, inds_s, vals_s, [u.astype(np.float64) for u in init_s], "auto")
+            line["error_vs_fp64_oracle"]["cp_grad_f32_max_mode_rel_fro"] = max(
+                oracle.rel_fro(gg32[n].cpu().numpy(), go[n]) for n in range(N))
+            line["error_vs_fp64_oracle"]["cp_grad_bf16_max_mode_rel_fro"] = max(
+                oracle.rel_fro(gg16[n].cpu().numpy(), go[n]) for n in range(N))
     print(json.dumps(line), flush=True)
 
 
