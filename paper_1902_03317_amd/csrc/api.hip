@@ -168,6 +168,36 @@ bool choose_shape(pasta_dtype dt, uint32_t R, uint32_t ldf, uint32_t ldo, const 
     return false;
 }
 
+// The segmented kernel's contiguous shapes address factor rows with 32-bit byte
+// offsets (row index times row bytes in a 24-bit multiply): every factor must
+// have fewer than 2^24 rows and fit in 4 GiB, else the generic strided shape
+// (64-bit addressing) runs instead.
+bool rows_fit32(uint64_t max_rows, uint32_t ldf, pasta_dtype dt)
+{
+    const uint64_t row_bytes = (uint64_t)ldf * (dt == PASTA_BF16 ? 2u : 4u);
+    return max_rows < (1ull << 24) && row_bytes < (1ull << 24) && max_rows * row_bytes <= (1ull << 32);
+}
+
+bool segmented_shape(pasta_dtype dt, uint32_t R, uint32_t ldf, uint32_t ldo, const void *const *facs, uint32_t nf,
+                     const void *out, uint64_t max_rows, KernelShape &s)
+{
+    if (!choose_shape(dt, R, ldf, ldo, facs, nf, out, s)) return false;
+    if (!s.strided && !rows_fit32(max_rows, ldf, dt)) {
+        if (R > 256) return false;
+        s.vec = 4;
+        s.lanes = 64;
+        s.strided = true;
+    }
+    return true;
+}
+
+uint64_t max_dim(const pasta_coo *X)
+{
+    uint64_t m = 0;
+    for (uint32_t k = 0; k < X->order; ++k) m = std::max<uint64_t>(m, X->dims[k]);
+    return m;
+}
+
 hipError_t launch_mttkrp(uint32_t N, const MttkrpLaunch &l, bool bf16, KernelShape s, bool fused, hipStream_t st)
 {
     switch (N - 1) {
@@ -275,7 +305,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     for (uint32_t k = 0; k < X->order; ++k)
         if (k != mode || fused) fl[nf++] = facs[k];
     KernelShape s;
-    if (!choose_shape(dt, rank, ldf, ldo, fl, nf, out, s)) return PASTA_EUNSUPPORTED;
+    if (!segmented_shape(dt, rank, ldf, ldo, fl, nf, out, max_dim(X), s)) return PASTA_EUNSUPPORTED;
     MttkrpPlan p;
     if (!plan_mttkrp(X->nnz, rank, s, p)) return PASTA_EUNSUPPORTED;
     if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
@@ -763,7 +793,7 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
             const void *fl[kMaxOrder];
             for (uint32_t k = 0; k < X->order; ++k) fl[k] = d_factors[k];
             KernelShape sh;
-            choose_shape(dtype, rank, ldf, ldg, fl, X->order, d_grads[0], sh);
+            segmented_shape(dtype, rank, ldf, ldg, fl, X->order, d_grads[0], max_dim(X), sh);
             MttkrpPlan p;
             plan_mttkrp(X->nnz, rank, sh, p);
             HIPCHK(launch_sum_f64(lp, p.nchunks, d_loss, st));
@@ -1105,7 +1135,7 @@ pasta_status pasta_ttm(const pasta_fibers *F, const void *d_U, pasta_dtype dtype
     if (!d_U || !d_out) return PASTA_EINVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     KernelShape s;
-    if (!choose_shape(dtype, rank, ldu, ldo, &d_U, 1, d_out, s)) return PASTA_EUNSUPPORTED;
+    if (!segmented_shape(dtype, rank, ldu, ldo, &d_U, 1, d_out, F->dim, s)) return PASTA_EUNSUPPORTED;
     MttkrpPlan p;
     if (!plan_mttkrp(F->nnz, rank, s, p)) return PASTA_EUNSUPPORTED;
     if (!d_work || work_bytes < p.part_bytes || ((uintptr_t)d_work % kAlign) != 0) return PASTA_EWORKSPACE;

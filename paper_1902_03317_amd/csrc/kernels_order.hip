@@ -48,6 +48,7 @@ struct MttkrpArgs {
     double *loss_part;
     uint64_t nnz;
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
+    uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
     float alpha;
 };
 
@@ -162,8 +163,26 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     // The loop below is unrolled three times with the buffers' roles rotated,
     // so no register holding a load in flight is ever copied (a copy would
     // have to wait for the load).
-    auto step = [&](Entries &E0, Entries &E1, Entries &E2, uint64_t p) {
-        const uint32_t navail = (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
+    // One 16-byte slice of factor row iu. Contiguous shapes add a 32-bit byte
+    // offset (24-bit row index times the row bytes) to the factor's base, which
+    // the host guarantees fits; the strided shape keeps 64-bit addressing.
+    auto gather = [&](int k, uint32_t iu, int jj, Packed &pk) {
+        if constexpr (STRIDED) {
+            S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, jj, a.rank, pk);
+        } else {
+            const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)jj * 16u;
+            const uint4 t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+            pk.w[0] = t.x;
+            pk.w[1] = t.y;
+            pk.w[2] = t.z;
+            pk.w[3] = t.w;
+        }
+    };
+    // FULL: every group's run is whole steps (a full chunk), so no step checks
+    // how many of its entries exist.
+    auto step = [&](Entries &E0, Entries &E1, Entries &E2, uint64_t p, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const uint32_t navail = FULL ? (uint32_t)U : (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
         // broadcast each entry to the group and issue all its gathers
         uint32_t ru[U];
         float vu[U];
@@ -180,14 +199,12 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                 if constexpr (kReuse) {
                     // the same factor row as the previous nonzero: keep it, no request
                     reuse[u][k] = iu == lastk[k];
-                    if ((uint32_t)u < navail) lastk[k] = iu;
-                    if ((uint32_t)u < navail && lane_on && !reuse[u][k])
-                        S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, j, a.rank, gp[u][k]);
+                    if (FULL || (uint32_t)u < navail) lastk[k] = iu;
+                    if ((FULL || (uint32_t)u < navail) && lane_on && !reuse[u][k]) gather(k, iu, j, gp[u][k]);
                 } else {
                     // branch-free: entries past the run read their (clamped, valid)
                     // row and idle lanes read slice 0; both results are discarded
-                    S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, lane_on ? j : 0, a.rank,
-                            gp[u][k]);
+                    gather(k, iu, lane_on ? j : 0, gp[u][k]);
                 }
             }
         }
@@ -196,7 +213,9 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
         load_entries(p + 2 * U, E2);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if ((uint32_t)u >= navail) break;
+            if constexpr (!FULL) {
+                if ((uint32_t)u >= navail) break;
+            }
             float q[VEC];
             if constexpr (kReuse) {
 #pragma unroll
@@ -254,12 +273,23 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     __builtin_amdgcn_sched_barrier(0);  // keep e0's loads ahead of e1's (in-order waits)
     load_entries(s0 + U, e1);
     resolve_values(e0);
-    for (uint64_t p = s0; p < s1; p += 3 * U) {
-        step(e0, e1, e2, p);
-        if (p + U >= s1) break;
-        step(e1, e2, e0, p + U);
-        if (p + 2 * U >= s1) break;
-        step(e2, e0, e1, p + 2 * U);
+    static_assert(256 % U == 0, "runs of whole steps in full chunks");
+    if (c1 - c0 == C && a.sub % U == 0) {  // wave-uniform
+        for (uint64_t p = s0; p < s1; p += 3 * U) {
+            step(e0, e1, e2, p, std::true_type{});
+            if (p + U >= s1) break;
+            step(e1, e2, e0, p + U, std::true_type{});
+            if (p + 2 * U >= s1) break;
+            step(e2, e0, e1, p + 2 * U, std::true_type{});
+        }
+    } else {
+        for (uint64_t p = s0; p < s1; p += 3 * U) {
+            step(e0, e1, e2, p, std::false_type{});
+            if (p + U >= s1) break;
+            step(e1, e2, e0, p + U, std::false_type{});
+            if (p + 2 * U >= s1) break;
+            step(e2, e0, e1, p + 2 * U, std::false_type{});
+        }
     }
 
     // ---- join the runs' edge rows across the G groups of the wave ----
@@ -560,6 +590,7 @@ hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool 
     a.rank = l.rank;
     a.sub = l.sub;
     a.nchunks = l.nchunks;
+    a.row_bytes = l.ldf * (bf16 ? 2u : 4u);
     a.alpha = l.alpha;
     return dispatch<MttkrpRun>(a, bf16, s, st, fused);
 }
