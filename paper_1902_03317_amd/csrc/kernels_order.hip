@@ -183,16 +183,13 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     auto step = [&](Entries &E0, Entries &E1, Entries &E2, uint64_t p, auto full) {
         constexpr bool FULL = decltype(full)::value;
         const uint32_t navail = FULL ? (uint32_t)U : (uint32_t)(s1 - p < (uint64_t)U ? s1 - p : (uint64_t)U);
-        // broadcast each entry to the group and issue all its gathers
-        uint32_t ru[U];
-        float vu[U];
+        // broadcast each entry's factor indices to the group and issue all its
+        // gathers; its row and value are broadcast later, where they are used
         Packed gp[U][NM1];
         bool reuse[U][NM1];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int src = gbase | (u % L);
-            ru[u] = (uint32_t)__shfl((int)E0.r[u / L], src);
-            vu[u] = __shfl(E0.v[u / L], src);
 #pragma unroll
             for (int k = 0; k < NM1; ++k) {
                 const uint32_t iu = (uint32_t)__shfl((int)E0.i[u / L][k], src);
@@ -216,6 +213,9 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
             if constexpr (!FULL) {
                 if ((uint32_t)u >= navail) break;
             }
+            const int src = gbase | (u % L);
+            const uint32_t ru = (uint32_t)__shfl((int)E0.r[u / L], src);
+            const float vu = __shfl(E0.v[u / L], src);
             float q[VEC];
             if constexpr (kReuse) {
 #pragma unroll
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                     for (int e = 0; e < VEC; ++e) q[e] *= t[e];
                 }
             }
-            if (ru[u] != cur) {
+            if (ru != cur) {
                 if (cur != kNoRow) {
                     if (!multi) {  // the run's first row may continue in earlier runs: keep it
 #pragma unroll
@@ -248,20 +248,20 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                         store_slice<VEC, STRIDED>(a.out + (uint64_t)cur * a.ldo, j, a.rank, acc, a.alpha);
                     }
                 }
-                cur = ru[u];
+                cur = ru;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
                 if constexpr (FUSED) {
                     if (lane_on) S::load_f(static_cast<const FT *>(a.facn) + (uint64_t)cur * a.ldf, j, a.rank, rowfac);
                 }
             }
-            float w = vu[u];
+            float w = vu;
             if constexpr (FUSED) {  // residual of the CP model at this nonzero
                 float d = 0.0f;
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) d += rowfac[e] * q[e];
                 d = group_sum<L>(lane_on ? d : 0.0f);
-                w = d - vu[u];
+                w = d - vu;
                 loss_run += w * w;
             }
 #pragma unroll
