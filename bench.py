@@ -11,7 +11,16 @@ One step is one pass of the whole hot path over one synthetic tensor:
      bf16 copies in the same pass).
 `value` is the MTTKRP throughput of step 2, nonzeros x modes / time, in
 Gnnz/s (the suite sums its MTTKRP times over all modes). Inputs are resident
-in GPU memory before timing starts.
+in GPU memory before timing starts. With --config 3 or 5 the step runs on the
+order-4 or order-5 workload (the CP step then on that tensor's own values).
+
+Outside the timed steps the line also reports, on the headline tensor: a
+CP-ALS sweep, fiber pre-processing, sparse TTM (R = 32) and TTV per mode,
+same-pattern element-wise and tensor-scalar operations and the general
+element-wise operation of the tensor with itself; the bandwidth of a plain
+device copy (the achievable streaming rate beside the spec peak); and, unless
+--no-cpu-baseline, the FP64 oracle timed on the host cores (all threads, and
+one thread on a sample) with the GPU results' errors against it.
 
 The roofline object prices the MTTKRP main kernel against the 8 TB/s HBM
 peak under the algorithmic bytes model B = (4N + 4 + (N-1) R s_f) bytes per
@@ -326,6 +335,19 @@ def main():
         if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == spec.name:
             traffic = tr.get("bytes_per_launch")
     ms_step = wall * 1e3 / args.steps
+    # achievable streaming bandwidth on this device: a plain 1 GiB device-to-device copy
+    cbuf = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cdst = torch.empty_like(cbuf)
+    cdst.copy_(cbuf)
+    ctimes = []
+    for _ in range(5):
+        a0, a1 = hip.event(), hip.event()
+        hip.record(a0, s_ptr)
+        cdst.copy_(cbuf)
+        hip.record(a1, s_ptr)
+        ctimes.append(hip.ms(a0, a1))
+    copy_gbps = 2 * cbuf.numel() * 4 / (sorted(ctimes)[2] * 1e-3) / 1e9
+    del cbuf, cdst
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -344,6 +366,7 @@ def main():
                    "values": spec.values, "seed": spec.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "copy_gbps": round(copy_gbps, 1),
                      "kernel": "mttkrp_seg_kernel", "bytes_per_nnz": bytes_alg_per_nnz(N, R, sf),
                      "launch_ms": [round(k, 4) for k in kern_ms]},
         "breakdown_ms": {"preprocess": round(sum(pre) / len(pre), 4), "mttkrp_all_modes": round(t_modes, 4),
@@ -459,6 +482,19 @@ def main():
         log("cpu baseline (oracle) ...")
         cb, (m, inds_s, vals_s, outs_o) = cpu_baseline(coo, U)
         line["cpu_baseline"] = cb
+        # the single-thread sequential oracle (the suite's speedup reference), on the first 2M nonzeros
+        import oracle
+        ms = min(coo.nnz, 2_000_000)
+        i1 = np.ascontiguousarray(coo.inds[:, :ms])
+        v1 = coo.vals[:ms].astype(np.float64)
+        U64 = [u.astype(np.float64) for u in U]
+        t1 = time.perf_counter()
+        for n in range(N):
+            oracle.mttkrp(coo.dims, i1, v1, U64, n, "seq")
+        t1 = time.perf_counter() - t1
+        line["cpu_baseline_1thread"] = {"value": round(N * ms / t1 / 1e9, 5), "unit": "Gnnz/s", "cores": 1,
+                                        "kind": "oracle", "sample": f"the first {ms} nonzeros, all {N} modes, "
+                                        f"sequential FP64 MTTKRP, {t1:.1f} s"}
         # error of the GPU path on the same sample vs the FP64 oracle results just computed
         import oracle
         Xs = X if m == coo.nnz else api.Coo(coo.dims, torch.from_numpy(inds_s.view(np.int32)).to(dev),
