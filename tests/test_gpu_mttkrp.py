@@ -152,7 +152,8 @@ def _layout(rows_per_nnz, dims, seed):
 
 @pytest.mark.parametrize("case", ["one_row", "every_nnz_own_row", "chunk_aligned", "chunk_plus_one",
                                   "chunk_minus_one", "sub_run_edges", "tail_only", "single_nnz", "empty_rows",
-                                  "lone_split_row_high_lane", "long_row_mid_chunk"])
+                                  "lone_split_row_high_lane", "long_row_mid_chunk", "short_mixed",
+                                  "tile_edges"])
 @pytest.mark.parametrize("R", [32, 64, 100])
 def test_adversarial_layouts(case, R):
     """Row layouts that stress the chunk and lane-group edges (mode 0 carries the layout)."""
@@ -188,6 +189,14 @@ def test_adversarial_layouts(case, R):
         # one row over ~150 chunks (level-one fixup blocks), ending inside a chunk
         rows = np.concatenate([np.zeros(100, int), np.ones(C * 147 + 123, int), np.full(50, 2)])
         dims = (3, 300, 200)
+    elif case == "short_mixed":
+        # rows of 1..20 nonzeros: several rows end inside most steps of a lane group
+        rows = np.repeat(np.arange(3000), rng.integers(1, 21, 3000))
+        dims = (3000, 300, 200)
+    elif case == "tile_edges":
+        # row lengths around 64 and around the steps of a lane group
+        rows = np.repeat(np.arange(400), np.resize([64, 63, 65, 8, 16, 7, 9, 128, 1, 127], 400))
+        dims = (400, 300, 200)
     elif case == "single_nnz":
         rows = np.array([3])
         dims = (6, 5, 4)
