@@ -180,6 +180,8 @@ def main():
                     help="factor storage of the MTTKRP step (arithmetic is fp32 either way)")
     ap.add_argument("--cache", default=os.environ.get("PASTA_BENCH_CACHE", ""),
                     help="directory for cached generated tensors (reused between runs)")
+    ap.add_argument("--mttkrp-form", choices=["auto", "run", "wave"], default="auto",
+                    help="MTTKRP kernel form (auto: wave-run form for long rows)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="run one plain device copy of this size (counter calibration) and exit")
     args = ap.parse_args()
@@ -213,6 +215,8 @@ def main():
         return
 
     hip = Hip()
+    from paper_1902_03317_amd._lib import lib as _plib
+    _plib.pasta_set_mttkrp_form({"auto": 0, "run": 1, "wave": 2}[args.mttkrp_form])
     spec = synth.CONFIGS[args.config]
     N, R = spec.order, spec.rank
     t0 = time.perf_counter()

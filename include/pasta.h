@@ -195,6 +195,16 @@ pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_
  * once and then disarmed; NULL disarms. Calls with nnz = 0 leave it armed. */
 pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop);
 
+/* Which form of the MTTKRP kernel pasta_mttkrp (and the CP-ALS sweep) runs,
+ * for every later call in the process: 0 = automatic (the default: the
+ * wave-run form when rows average at least 32 nonzeros, else the run form),
+ * 1 = the run form (each lane group walks its own run of nonzeros), 2 = the
+ * wave-run form (a wave walks one run, its groups taking consecutive
+ * nonzeros). Both give the same results to rounding; value overrides, the
+ * fused CP gradient, TTM and the strided shape always use the run form. For
+ * tuning and tests; not thread-safe against concurrent calls. */
+pasta_status pasta_set_mttkrp_form(int form);
+
 /* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
  * derivative held on the device (no host round trip). */
 pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream);

@@ -62,6 +62,9 @@ constexpr size_t kAlign = 256;
 #endif
 constexpr uint32_t kSub = PASTA_SUB;      // nonzeros per lane group per chunk
 constexpr uint32_t kSampleTilesPerWave = 16;
+constexpr uint32_t kWaveChunk = 2048;    // nonzeros per chunk of the wave-run form
+constexpr uint64_t kWaveMinRowLen = 32;  // average nonzeros per row from which it is chosen
+int g_mttkrp_form = 0;                   // 0 automatic, 1 run form, 2 wave-run form
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -250,12 +253,12 @@ struct MttkrpPlan {
     size_t part_bytes;
 };
 
-bool plan_mttkrp(uint64_t nnz, uint32_t rank, KernelShape s, MttkrpPlan &p)
+bool plan_mttkrp(uint64_t nnz, uint32_t rank, KernelShape s, MttkrpPlan &p, bool wave = false)
 {
     p.shape = s;
     const uint32_t G = 64u / (uint32_t)s.lanes;
-    p.sub = kSub;
-    p.chunk = (uint64_t)p.sub * G;
+    p.sub = wave ? kWaveChunk : kSub;
+    p.chunk = wave ? (uint64_t)kWaveChunk : (uint64_t)p.sub * G;
     const uint64_t nch = (nnz + p.chunk - 1) / p.chunk;
     if (nch > 0x7FFFFFFFull) return false;
     p.nchunks = (uint32_t)nch;
@@ -306,8 +309,12 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
         if (k != mode || fused) fl[nf++] = facs[k];
     KernelShape s;
     if (!segmented_shape(dt, rank, ldf, ldo, fl, nf, out, max_dim(X), s)) return PASTA_EUNSUPPORTED;
+    // the wave-run form for plain MTTKRP on long rows (contiguous shapes only)
+    const bool wave_ok = !fused && !ovr && !s.strided;
+    const bool wave = wave_ok && (g_mttkrp_form == 2 ||
+                                  (g_mttkrp_form == 0 && X->nnz >= kWaveMinRowLen * X->dims[mode]));
     MttkrpPlan p;
-    if (!plan_mttkrp(X->nnz, rank, s, p)) return PASTA_EUNSUPPORTED;
+    if (!plan_mttkrp(X->nnz, rank, s, p, wave)) return PASTA_EUNSUPPORTED;
     if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
         return PASTA_EWORKSPACE;
     const auto &md = X->mode[mode];
@@ -334,6 +341,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     l.sub = p.sub;
     l.nchunks = p.nchunks;
     l.alpha = alpha;
+    l.wave = wave;
     if (X->nnz > 0) {
         hipEvent_t e0 = g_ev_start, e1 = g_ev_stop;
         g_ev_start = g_ev_stop = nullptr;
@@ -902,6 +910,13 @@ pasta_status pasta_cp_als_sweep(const pasta_coo *X, float *const *d_factors, uin
         HIPCHK(launch_fit(M, rank, d_factors[last], ldf, d_lambda, X->dims[last], rank, grams, X->order, inner, xn2,
                           d_fit, st));
     }
+    return PASTA_OK;
+}
+
+pasta_status pasta_set_mttkrp_form(int form)
+{
+    if (form < 0 || form > 2) return PASTA_EINVAL;
+    g_mttkrp_form = form;
     return PASTA_OK;
 }
 

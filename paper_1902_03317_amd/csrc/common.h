@@ -157,9 +157,10 @@ struct MttkrpLaunch {
     double *loss_part;               // fused: one fp64 partial per chunk (nullable)
     uint64_t nnz;
     uint32_t ldf, ldo, ldp, rank;
-    uint32_t sub;                    // nonzeros per group per chunk
+    uint32_t sub;                    // nonzeros per group per chunk (wave form: per chunk)
     uint32_t nchunks;
     float alpha;
+    bool wave;                       // the wave-run form (plain MTTKRP, contiguous shapes)
 };
 
 struct SampleLaunch {

@@ -352,6 +352,192 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Wave-run form, for streams whose rows are long. A wave owns one chunk of
+// `sub` consecutive nonzeros and walks it G at a time: in each step, group g
+// takes the g-th of G consecutive nonzeros. Nonzeros next to each other in the
+// mode order often name the same factor row (the order's second key is the
+// previous mode), so those gathers land in one instruction and share its
+// cache-line request. The row being summed is the same for the whole wave;
+// each group keeps its own share of it in registers, and the shares are added
+// across groups (shuffles) only when the row ends. A tile of 64 entries is
+// loaded with one coalesced load per stream and broadcast from the lane that
+// holds each entry; `US` steps' gathers go out together, and the entries two
+// tiles ahead are loaded behind them. Rows crossing the chunk's edges leave
+// partials in the same slots as the run form, for the same fixup.
+// ---------------------------------------------------------------------------
+template <typename FT, int VEC, int L>
+__global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
+{
+    constexpr int G = kWave / L;                 // nonzeros per step
+    constexpr int US = L < kStep ? L : kStep;    // steps whose gathers go out together
+    constexpr int MS = L / US;                   // such groups of steps per tile of 64 entries
+    using S = Slice<FT, VEC, false>;
+    using Packed = typename S::Packed;
+    const int lane = threadIdx.x & 63;
+    const uint32_t chunk = chunk_of_wave(gridDim.x);
+    if (chunk >= a.nchunks) return;  // whole wave leaves together
+    const int g = lane / L, j = lane % L;
+    const uint64_t C = a.sub;
+    const uint64_t c0 = (uint64_t)chunk * C;
+    const uint64_t c1 = c0 + C < a.nnz ? c0 + C : a.nnz;
+    const bool lane_on = S::active(j, a.rank);
+    const uint32_t cfirst = a.row[c0], clast = a.row[c1 - 1];
+    const bool before = c0 > 0 && a.row[c0 - 1] == cfirst;
+    const bool after = c1 < a.nnz && a.row[c1] == clast;
+    uint32_t cur = cfirst;  // the row being summed (wave-uniform)
+    float acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+
+    // total of row `cur` over every group (plus `extra` from this step), stored by group 0
+    auto close_row = [&](const float (&extra)[VEC]) __attribute__((always_inline)) {
+        float t[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) t[e] = acc[e] + extra[e];
+#pragma unroll
+        for (int off = L; off < kWave; off <<= 1)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) t[e] += __shfl_xor(t[e], off);
+        if (g == 0 && lane_on) {
+            if (cur == cfirst && before)
+                store_slice<VEC, false>(a.part + (uint64_t)(2 * (uint64_t)chunk) * a.ldp, j, a.rank, t, 1.0f);
+            else if (cur == clast && after)
+                store_slice<VEC, false>(a.part + (uint64_t)(2 * (uint64_t)chunk + 1) * a.ldp, j, a.rank, t, 1.0f);
+            else
+                store_slice<VEC, false>(a.out + (uint64_t)cur * a.ldo, j, a.rank, t, a.alpha);
+        }
+    };
+    auto gather = [&](int k, uint32_t iu, Packed &pk) __attribute__((always_inline)) {
+        const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)(lane_on ? j : 0) * 16u;
+        const uint4 t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+        pk.w[0] = t.x;
+        pk.w[1] = t.y;
+        pk.w[2] = t.z;
+        pk.w[3] = t.w;
+    };
+    struct Entries {
+        uint32_t r, i[NM1];
+        float v;
+    };
+    const uint64_t last = a.nnz - 1;
+    // entries past the chunk carry its last row and no value
+    auto load_tile = [&](uint64_t base, Entries &E) __attribute__((always_inline)) {
+        const uint64_t q0 = base + (uint64_t)lane;
+        const uint64_t q = q0 < last ? q0 : last;
+        E.r = stream_load(a.row + q);
+#pragma unroll
+        for (int k = 0; k < NM1; ++k) E.i[k] = stream_load(a.idx[k] + q);
+        E.v = stream_load(a.vals + q);
+        if (q0 >= c1) {
+            E.r = clast;
+            E.v = 0.0f;
+        }
+    };
+    // One tile: MS groups of US steps; `next` is loaded behind the first group's gathers.
+    auto tile = [&](const Entries &E, Entries &next, uint64_t base, auto full) __attribute__((always_inline)) {
+        constexpr bool FULLT = decltype(full)::value;
+#pragma unroll
+        for (int m = 0; m < MS; ++m) {
+            Packed gp[US][NM1];
+#pragma unroll
+            for (int u = 0; u < US; ++u) {
+                const int src = (m * US + u) * G + g;
+#pragma unroll
+                for (int k = 0; k < NM1; ++k) gather(k, (uint32_t)__shfl((int)E.i[k], src), gp[u][k]);
+            }
+            if (m == 0) {
+                __builtin_amdgcn_sched_barrier(0);  // the next loads go out after these gathers
+                load_tile(base + 2 * (uint64_t)kWave, next);
+            }
+            // the row of the group of steps' last entry decides the path for all of them
+            const uint32_t mlast = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m + 1) * US * G - 1);
+            if (mlast == cur) {  // the common case: every entry is in the current row
+#pragma unroll
+                for (int u = 0; u < US; ++u) {
+                    const int src = (m * US + u) * G + g;
+                    const float vu = __shfl(E.v, src);
+                    float q[VEC];
+                    S::unpack(gp[u][0], q);
+#pragma unroll
+                    for (int k = 1; k < NM1; ++k) {
+                        float t[VEC];
+                        S::unpack(gp[u][k], t);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+                    }
+                    if constexpr (FULLT) {
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] += vu * q[e];
+                    } else {
+                        const bool on = base + (uint64_t)src < c1;
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] = on ? acc[e] + vu * q[e] : acc[e];
+                    }
+                }
+            } else {  // rows end inside this group of steps
+#pragma unroll
+                for (int u = 0; u < US; ++u) {
+                    const int src = (m * US + u) * G + g;
+                    const uint32_t ru = (uint32_t)__shfl((int)E.r, src);
+                    const float vu = __shfl(E.v, src);
+                    const bool on = FULLT || base + (uint64_t)src < c1;
+                    float q[VEC];
+                    S::unpack(gp[u][0], q);
+#pragma unroll
+                    for (int k = 1; k < NM1; ++k) {
+                        float t[VEC];
+                        S::unpack(gp[u][k], t);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+                    }
+                    float contrib[VEC];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) contrib[e] = on ? vu * q[e] : 0.0f;
+                    const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m * US + u) * G + G - 1);
+                    while (cur != rl) {  // wave-uniform: close every row that ends in this step
+                        float extra[VEC];
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) extra[e] = ru == cur ? contrib[e] : 0.0f;
+                        close_row(extra);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+                        // the next row: that of the first group past the current one. Only the
+                        // first lane of each group votes, so the lowest set bit is that lane.
+                        const uint64_t ahead = __ballot(j == 0 && ru > cur);
+                        const int first_lane = __ffsll((long long)ahead) - 1;
+                        cur = (uint32_t)__builtin_amdgcn_readlane((int)ru, first_lane);
+                    }
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) acc[e] += ru == cur ? contrib[e] : 0.0f;
+                }
+            }
+        }
+    };
+    Entries e0, e1, e2;
+    load_tile(c0, e0);
+    __builtin_amdgcn_sched_barrier(0);  // keep e0's loads ahead of e1's (in-order waits)
+    load_tile(c0 + kWave, e1);
+    const uint64_t ntiles = (c1 - c0 + kWave - 1) / kWave;
+    auto walk = [&](auto full) __attribute__((always_inline)) {
+        for (uint64_t t = 0; t < ntiles; t += 3) {
+            tile(e0, e2, c0 + t * kWave, full);
+            if (t + 1 >= ntiles) break;
+            tile(e1, e0, c0 + (t + 1) * kWave, full);
+            if (t + 2 >= ntiles) break;
+            tile(e2, e1, c0 + (t + 2) * kWave, full);
+        }
+    };
+    if (c1 - c0 == C)  // wave-uniform
+        walk(std::true_type{});
+    else
+        walk(std::false_type{});
+    float zero[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) zero[e] = 0.0f;
+    close_row(zero);  // the last row of the chunk
+}
+
+// ---------------------------------------------------------------------------
 // Sampled CP model: mhat_m = sum_r prod_k U^(k)[i_k(m), r], caller order.
 // A wave takes 64 consecutive nonzeros at a time (coalesced index loads, one
 // per lane); group g handles the L of them held by its own lanes.
@@ -494,9 +680,15 @@ unsigned clamp_grid(uint64_t g, uint64_t cap)
 }
 
 template <typename FT, int VEC, int L, bool STRIDED>
-hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, hipStream_t st)
+hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, bool wave, hipStream_t st)
 {
     const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
+    if constexpr (!STRIDED) {
+        if (wave && !fused && !args.perm) {
+            mttkrp_wave_kernel<FT, VEC, L><<<grid, 256, 0, st>>>(args);
+            return hipGetLastError();
+        }
+    }
     if (fused)
         mttkrp_seg_kernel<FT, VEC, L, STRIDED, true, false><<<grid, 256, 0, st>>>(args);
     else if (args.perm)
@@ -551,7 +743,10 @@ hipError_t dispatch(const Args &args, bool bf16, KernelShape s, hipStream_t st, 
 
 template <typename FT, int VEC, int L, bool STRIDED>
 struct MttkrpRun {
-    static hipError_t run(const MttkrpArgs &a, hipStream_t st, bool fused) { return run_mttkrp<FT, VEC, L, STRIDED>(a, fused, st); }
+    static hipError_t run(const MttkrpArgs &a, hipStream_t st, bool fused, bool wave)
+    {
+        return run_mttkrp<FT, VEC, L, STRIDED>(a, fused, wave, st);
+    }
 };
 template <typename FT, int VEC, int L, bool STRIDED>
 struct SampleRun {
@@ -592,7 +787,7 @@ hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool 
     a.nchunks = l.nchunks;
     a.row_bytes = l.ldf * (bf16 ? 2u : 4u);
     a.alpha = l.alpha;
-    return dispatch<MttkrpRun>(a, bf16, s, st, fused);
+    return dispatch<MttkrpRun>(a, bf16, s, st, fused, l.wave);
 }
 
 hipError_t PASTA_CAT(launch_sample_nm1_, PASTA_NM1)(const SampleLaunch &l, bool bf16, KernelShape s, hipStream_t st)

@@ -62,14 +62,23 @@ def test_mode_orders_full_size(full):
         assert np.array_equal(svals.cpu().numpy(), coo.vals[p])
 
 
+@pytest.fixture(params=["run", "wave"])
+def form(request):
+    from paper_1902_03317_amd._lib import lib
+    lib.pasta_set_mttkrp_form({"run": 1, "wave": 2}[request.param])
+    yield request.param
+    lib.pasta_set_mttkrp_form(0)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-def test_sampled_rows_full_size(full, dtype):
+def test_sampled_rows_full_size(full, dtype, form):
+    """Both kernel forms; rows crossing the chunk edges of either form are sampled."""
     spec, coo, X = full
     U = synth.make_factors(spec)
     fd = factors_dev(U, dtype)
     U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
     rng = np.random.default_rng(31)
-    C = 256 * 64 // (8 if dtype == torch.float32 else 4)  # nonzeros per chunk of this launch shape
+    C = 2048 if form == "wave" else 256 * 64 // (8 if dtype == torch.float32 else 4)  # nonzeros per chunk
     for n in range(coo.order):
         out = torch.empty((coo.dims[n], spec.rank), device=DEV)
         from paper_1902_03317_amd import api

@@ -24,6 +24,16 @@ def api():
     return a
 
 
+@pytest.fixture(autouse=True, params=["run", "wave"])
+def mttkrp_form(request):
+    """Every test of this module runs with both forms of the MTTKRP kernel (each lane group on
+    its own run of nonzeros, or a whole wave on one run)."""
+    from paper_1902_03317_amd._lib import lib
+    lib.pasta_set_mttkrp_form({"run": 1, "wave": 2}[request.param])
+    yield request.param
+    lib.pasta_set_mttkrp_form(0)
+
+
 def check_preprocess(coo, X):
     orders = oracle.mode_orders(coo.inds)
     for n in range(coo.order):
@@ -155,10 +165,14 @@ def _layout(rows_per_nnz, dims, seed):
                                   "lone_split_row_high_lane", "long_row_mid_chunk", "short_mixed",
                                   "tile_edges"])
 @pytest.mark.parametrize("R", [32, 64, 100])
-def test_adversarial_layouts(case, R):
-    """Row layouts that stress the chunk and lane-group edges (mode 0 carries the layout)."""
+def test_adversarial_layouts(case, R, mttkrp_form):
+    """Row layouts that stress the chunk, tile and lane-group edges of the kernel form under
+    test (mode 0 carries the layout)."""
     rng = np.random.default_rng(sum(map(ord, case)))
-    C = 256 * (64 // (8 if R == 32 else 16)) if R != 100 else 256  # nonzeros per chunk of mode 0
+    if mttkrp_form == "wave" and R != 100:
+        C = 2048  # nonzeros per chunk of the wave-run form (R = 100 takes the strided run form)
+    else:
+        C = 256 * (64 // (8 if R == 32 else 16)) if R != 100 else 256  # nonzeros per chunk of mode 0
     if case == "one_row":
         rows = np.full(50_000, 7)
         dims = (10, 300, 200)
