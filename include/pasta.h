@@ -195,13 +195,14 @@ pasta_status pasta_cast_f32_to_bf16(const float *d_src, uint16_t *d_dst, uint64_
  * once and then disarmed; NULL disarms. Calls with nnz = 0 leave it armed. */
 pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop);
 
-/* Which form of the MTTKRP kernel pasta_mttkrp (and the CP-ALS sweep) runs,
+/* Which form of the MTTKRP kernel the MTTKRP-based calls run,
  * for every later call in the process: 0 = automatic (the default: the
  * wave-run form when rows average at least 32 nonzeros, else the run form),
  * 1 = the run form (each lane group walks its own run of nonzeros), 2 = the
  * wave-run form (a wave walks one run, its groups taking consecutive
- * nonzeros). Both give the same results to rounding; value overrides, the
- * fused CP gradient, TTM and the strided shape always use the run form. For
+ * nonzeros). Both give the same results to rounding; it applies to
+ * pasta_mttkrp (with or without a value override), pasta_cp_grad and the
+ * CP-ALS sweep; TTM and the strided shape always use the run form. For
  * tuning and tests; not thread-safe against concurrent calls. */
 pasta_status pasta_set_mttkrp_form(int form);
 

@@ -253,6 +253,13 @@ struct MttkrpPlan {
     size_t part_bytes;
 };
 
+// The wave-run form on long rows (contiguous shapes only), unless a form is forced.
+bool use_wave(const KernelShape &s, uint64_t nnz, uint64_t rows)
+{
+    if (s.strided || g_mttkrp_form == 1) return false;
+    return g_mttkrp_form == 2 || nnz >= kWaveMinRowLen * rows;
+}
+
 bool plan_mttkrp(uint64_t nnz, uint32_t rank, KernelShape s, MttkrpPlan &p, bool wave = false)
 {
     p.shape = s;
@@ -309,10 +316,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
         if (k != mode || fused) fl[nf++] = facs[k];
     KernelShape s;
     if (!segmented_shape(dt, rank, ldf, ldo, fl, nf, out, max_dim(X), s)) return PASTA_EUNSUPPORTED;
-    // the wave-run form for plain MTTKRP on long rows (contiguous shapes only)
-    const bool wave_ok = !fused && !ovr && !s.strided;
-    const bool wave = wave_ok && (g_mttkrp_form == 2 ||
-                                  (g_mttkrp_form == 0 && X->nnz >= kWaveMinRowLen * X->dims[mode]));
+    const bool wave = use_wave(s, X->nnz, X->dims[mode]);
     MttkrpPlan p;
     if (!plan_mttkrp(X->nnz, rank, s, p, wave)) return PASTA_EUNSUPPORTED;
     if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
@@ -803,7 +807,7 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
             KernelShape sh;
             segmented_shape(dtype, rank, ldf, ldg, fl, X->order, d_grads[0], max_dim(X), sh);
             MttkrpPlan p;
-            plan_mttkrp(X->nnz, rank, sh, p);
+            plan_mttkrp(X->nnz, rank, sh, p, use_wave(sh, X->nnz, X->dims[0]));
             HIPCHK(launch_sum_f64(lp, p.nchunks, d_loss, st));
         }
     }

@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 // tiles ahead are loaded behind them. Rows crossing the chunk's edges leave
 // partials in the same slots as the run form, for the same fixup.
 // ---------------------------------------------------------------------------
-template <typename FT, int VEC, int L>
+template <typename FT, int VEC, int L, bool FUSED, bool OVR>
 __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;                 // nonzeros per step
@@ -388,6 +388,19 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     float acc[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = 0.0f;
+    // fused: the U^(n) slice of a row, and this group's sum of squared residuals
+    // (one term per step: chunk / G terms in fp32, then fp64 across the groups)
+    auto load_rowfac = [&](uint32_t r, float (&rf)[VEC]) __attribute__((always_inline)) {
+        if (lane_on) {
+            S::load_f(static_cast<const FT *>(a.facn) + (uint64_t)r * a.ldf, j, a.rank, rf);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) rf[e] = 0.0f;
+        }
+    };
+    float rowfac[VEC];
+    if constexpr (FUSED) load_rowfac(cur, rowfac);
+    float loss_run = 0.0f;
 
     // total of row `cur` over every group (plus `extra` from this step), stored by group 0
     auto close_row = [&](const float (&extra)[VEC]) __attribute__((always_inline)) {
@@ -415,26 +428,39 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
         pk.w[2] = t.z;
         pk.w[3] = t.w;
     };
+    // the CP model's residual at a nonzero whose row slice of U^(n) is rf, and the
+    // product q of its other rows: sum_r rf[r] q[r] - x (group reduction, fixed order)
+    auto residual = [&](const float (&rf)[VEC], const float (&q)[VEC], float x) __attribute__((always_inline)) {
+        float d = 0.0f;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d += rf[e] * q[e];
+        return group_sum<L>(lane_on ? d : 0.0f) - x;
+    };
     struct Entries {
         uint32_t r, i[NM1];
-        float v;
+        float v;  // with a value override: the position in caller order until resolved
     };
     const uint64_t last = a.nnz - 1;
-    // entries past the chunk carry its last row and no value
+    // entries past the chunk carry its last row (their contributions are masked off)
     auto load_tile = [&](uint64_t base, Entries &E) __attribute__((always_inline)) {
         const uint64_t q0 = base + (uint64_t)lane;
         const uint64_t q = q0 < last ? q0 : last;
         E.r = stream_load(a.row + q);
 #pragma unroll
         for (int k = 0; k < NM1; ++k) E.i[k] = stream_load(a.idx[k] + q);
-        E.v = stream_load(a.vals + q);
-        if (q0 >= c1) {
-            E.r = clast;
-            E.v = 0.0f;
-        }
+        if constexpr (OVR)
+            E.v = __uint_as_float(stream_load(a.perm + q));
+        else
+            E.v = stream_load(a.vals + q);
+        if (q0 >= c1) E.r = clast;
     };
-    // One tile: MS groups of US steps; `next` is loaded behind the first group's gathers.
-    auto tile = [&](const Entries &E, Entries &next, uint64_t base, auto full) __attribute__((always_inline)) {
+    auto resolve = [&](Entries &E) __attribute__((always_inline)) {
+        if constexpr (OVR) E.v = a.vals[__float_as_uint(E.v)];
+    };
+    // One tile: MS groups of US steps. After the first group's gathers go out, the
+    // next tile's values are resolved and the tile after it is loaded.
+    auto tile = [&](const Entries &E, Entries &follow, Entries &target, uint64_t base, auto full)
+                    __attribute__((always_inline)) {
         constexpr bool FULLT = decltype(full)::value;
 #pragma unroll
         for (int m = 0; m < MS; ++m) {
@@ -447,7 +473,8 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
             }
             if (m == 0) {
                 __builtin_amdgcn_sched_barrier(0);  // the next loads go out after these gathers
-                load_tile(base + 2 * (uint64_t)kWave, next);
+                resolve(follow);
+                load_tile(base + 2 * (uint64_t)kWave, target);
             }
             // the row of the group of steps' last entry decides the path for all of them
             const uint32_t mlast = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m + 1) * US * G - 1);
@@ -456,6 +483,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                 for (int u = 0; u < US; ++u) {
                     const int src = (m * US + u) * G + g;
                     const float vu = __shfl(E.v, src);
+                    const bool on = FULLT || base + (uint64_t)src < c1;
                     float q[VEC];
                     S::unpack(gp[u][0], q);
 #pragma unroll
@@ -465,13 +493,17 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) q[e] *= t[e];
                     }
+                    float w = vu;
+                    if constexpr (FUSED) {
+                        w = residual(rowfac, q, vu);
+                        loss_run += on ? w * w : 0.0f;
+                    }
                     if constexpr (FULLT) {
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[e] += vu * q[e];
+                        for (int e = 0; e < VEC; ++e) acc[e] += w * q[e];
                     } else {
-                        const bool on = base + (uint64_t)src < c1;
 #pragma unroll
-                        for (int e = 0; e < VEC; ++e) acc[e] = on ? acc[e] + vu * q[e] : acc[e];
+                        for (int e = 0; e < VEC; ++e) acc[e] = on ? acc[e] + w * q[e] : acc[e];
                     }
                 }
             } else {  // rows end inside this group of steps
@@ -490,10 +522,18 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 #pragma unroll
                         for (int e = 0; e < VEC; ++e) q[e] *= t[e];
                     }
+                    float w = vu;
+                    if constexpr (FUSED) {  // each group's own row slice of U^(n)
+                        float rf[VEC];
+                        load_rowfac(ru, rf);
+                        w = residual(rf, q, vu);
+                        loss_run += on ? w * w : 0.0f;
+                    }
                     float contrib[VEC];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e) contrib[e] = on ? vu * q[e] : 0.0f;
+                    for (int e = 0; e < VEC; ++e) contrib[e] = on ? w * q[e] : 0.0f;
                     const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m * US + u) * G + G - 1);
+                    const bool moved = cur != rl;
                     while (cur != rl) {  // wave-uniform: close every row that ends in this step
                         float extra[VEC];
 #pragma unroll
@@ -509,6 +549,9 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                     }
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) acc[e] += ru == cur ? contrib[e] : 0.0f;
+                    if constexpr (FUSED) {
+                        if (moved) load_rowfac(cur, rowfac);
+                    }
                 }
             }
         }
@@ -517,14 +560,15 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     load_tile(c0, e0);
     __builtin_amdgcn_sched_barrier(0);  // keep e0's loads ahead of e1's (in-order waits)
     load_tile(c0 + kWave, e1);
+    resolve(e0);
     const uint64_t ntiles = (c1 - c0 + kWave - 1) / kWave;
     auto walk = [&](auto full) __attribute__((always_inline)) {
         for (uint64_t t = 0; t < ntiles; t += 3) {
-            tile(e0, e2, c0 + t * kWave, full);
+            tile(e0, e1, e2, c0 + t * kWave, full);
             if (t + 1 >= ntiles) break;
-            tile(e1, e0, c0 + (t + 1) * kWave, full);
+            tile(e1, e2, e0, c0 + (t + 1) * kWave, full);
             if (t + 2 >= ntiles) break;
-            tile(e2, e1, c0 + (t + 2) * kWave, full);
+            tile(e2, e0, e1, c0 + (t + 2) * kWave, full);
         }
     };
     if (c1 - c0 == C)  // wave-uniform
@@ -535,6 +579,12 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 #pragma unroll
     for (int e = 0; e < VEC; ++e) zero[e] = 0.0f;
     close_row(zero);  // the last row of the chunk
+    if constexpr (FUSED) {
+        if (a.loss_part) {  // every lane of a group holds its sum: count it once per group
+            const double tot = wave_sum_f64(j == 0 ? 0.5 * (double)loss_run : 0.0);
+            if (lane == 0) a.loss_part[chunk] = tot;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -684,8 +734,13 @@ hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, bool wave, hipStream_t
 {
     const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
     if constexpr (!STRIDED) {
-        if (wave && !fused && !args.perm) {
-            mttkrp_wave_kernel<FT, VEC, L><<<grid, 256, 0, st>>>(args);
+        if (wave) {
+            if (fused)
+                mttkrp_wave_kernel<FT, VEC, L, true, false><<<grid, 256, 0, st>>>(args);
+            else if (args.perm)
+                mttkrp_wave_kernel<FT, VEC, L, false, true><<<grid, 256, 0, st>>>(args);
+            else
+                mttkrp_wave_kernel<FT, VEC, L, false, false><<<grid, 256, 0, st>>>(args);
             return hipGetLastError();
         }
     }

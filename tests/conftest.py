@@ -19,6 +19,16 @@ def oracle_lib():
     return oracle
 
 
+@pytest.fixture(params=["run", "wave"])
+def mttkrp_form(request):
+    """Runs a test with each form of the MTTKRP kernel forced (each lane group on its own
+    run of nonzeros, or a whole wave on one run), then restores the automatic choice."""
+    from paper_1902_03317_amd._lib import lib
+    lib.pasta_set_mttkrp_form({"run": 1, "wave": 2}[request.param])
+    yield request.param
+    lib.pasta_set_mttkrp_form(0)
+
+
 def gpu_available():
     try:
         import torch

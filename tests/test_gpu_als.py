@@ -7,7 +7,7 @@ import oracle
 from helpers import DEV, factors_dev, oracle_factors, rel, upload
 from paper_1902_03317_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("mttkrp_form")]
 
 
 def api():

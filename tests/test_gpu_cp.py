@@ -10,7 +10,7 @@ from oracle import brute
 from helpers import DEV, coo_from_arrays, factors_dev, oracle_factors, rel, to_dev, upload
 from paper_1902_03317_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("mttkrp_form")]
 
 
 def api():

@@ -62,35 +62,68 @@ def test_mode_orders_full_size(full):
         assert np.array_equal(svals.cpu().numpy(), coo.vals[p])
 
 
-@pytest.fixture(params=["run", "wave"])
-def form(request):
-    from paper_1902_03317_amd._lib import lib
-    lib.pasta_set_mttkrp_form({"run": 1, "wave": 2}[request.param])
-    yield request.param
-    lib.pasta_set_mttkrp_form(0)
+def _rows_to_check(coo, n, C, rng):
+    """The longest row of mode n, 12 random rows and 8 rows that cross a chunk edge
+    (chunks of C nonzeros of the sorted stream)."""
+    counts = np.bincount(coo.inds[n], minlength=coo.dims[n])
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    crossing = np.flatnonzero(((starts[:-1] // C) != ((starts[1:] - 1) // C)) & (counts > 0))
+    rows = {int(np.argmax(counts))} | set(int(r) for r in rng.choice(coo.dims[n], 12, replace=False))
+    rows |= set(int(r) for r in rng.choice(crossing, min(8, crossing.size), replace=False))
+    return sorted(rows), counts
+
+
+def _chunk(form, dtype):
+    """Nonzeros per chunk of the kernel form at rank 32."""
+    return 2048 if form == "wave" else 256 * 64 // (8 if dtype == torch.float32 else 4)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
-def test_sampled_rows_full_size(full, dtype, form):
+def test_sampled_rows_full_size(full, dtype, mttkrp_form):
     """Both kernel forms; rows crossing the chunk edges of either form are sampled."""
     spec, coo, X = full
     U = synth.make_factors(spec)
     fd = factors_dev(U, dtype)
     U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
     rng = np.random.default_rng(31)
-    C = 2048 if form == "wave" else 256 * 64 // (8 if dtype == torch.float32 else 4)  # nonzeros per chunk
     for n in range(coo.order):
         out = torch.empty((coo.dims[n], spec.rank), device=DEV)
         from paper_1902_03317_amd import api
         api.mttkrp(X, fd, n, out=out)
         got = out.cpu().numpy().astype(np.float64)
-        counts = np.bincount(coo.inds[n], minlength=coo.dims[n])
-        starts = np.concatenate([[0], np.cumsum(counts)])
-        crossing = np.flatnonzero(((starts[:-1] // C) != ((starts[1:] - 1) // C)) & (counts > 0))
-        rows = {int(np.argmax(counts))} | set(int(r) for r in rng.choice(coo.dims[n], 12, replace=False))
-        rows |= set(int(r) for r in rng.choice(crossing, min(8, crossing.size), replace=False))
-        for r in sorted(rows):
+        rows, counts = _rows_to_check(coo, n, _chunk(mttkrp_form, dtype), rng)
+        for r in rows:
             want = _row_oracle(coo, U64, n, r)
+            if not np.any(want):
+                assert not np.any(got[r])
+                continue
+            assert rel(got[r], want) <= 1e-5, f"mode {n} row {r} ({counts[r]} nonzeros)"
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_cp_grad_full_size(full, dtype, mttkrp_form):
+    """The fused CP gradient at full size, both kernel forms: the loss against the oracle's
+    over all 50M nonzeros, and sampled gradient rows (the residual-weighted MTTKRP of the
+    row's own nonzeros, residuals from the oracle)."""
+    spec, coo, X = full
+    from paper_1902_03317_amd import api
+    U = synth.make_factors(spec)
+    fd = factors_dev(U, dtype)
+    U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
+    loss, grads = api.cp_grad(X, fd)
+    wl, resid = oracle.cp_loss(coo.dims, coo.inds, coo.vals, U64)
+    assert abs(loss.item() - wl) <= 1e-5 * wl
+    rng = np.random.default_rng(37)
+    for n in range(coo.order):
+        got = grads[n].cpu().numpy().astype(np.float64)
+        rows, counts = _rows_to_check(coo, n, _chunk(mttkrp_form, dtype), rng)
+        for r in rows:
+            sel = np.flatnonzero(coo.inds[n] == r)
+            inds = coo.inds[:, sel].copy()
+            inds[n] = 0
+            dims = list(coo.dims)
+            dims[n] = 1
+            want = oracle.mttkrp(dims, inds, resid[sel], U64, n)[0]
             if not np.any(want):
                 assert not np.any(got[r])
                 continue
@@ -203,14 +236,15 @@ def _sampled_rows(spec, coo, X, dtype, seed, nrand=6, ncross=4):
     rng = np.random.default_rng(seed)
     R = spec.rank
     lanes = max(1, R * (2 if dtype == torch.bfloat16 else 4) // 16)
-    C = 256 * (64 // lanes)
+    Cs = (256 * (64 // lanes), 2048)  # nonzeros per chunk of the run form and of the wave-run form
     worst = 0.0
     for n in range(coo.order):
         out = api.mttkrp(X, fd, n).cpu().numpy().astype(np.float64)
         counts = np.bincount(coo.inds[n], minlength=coo.dims[n])
         starts = np.concatenate([[0], np.cumsum(counts)])
         nonempty = np.flatnonzero(counts)
-        crossing = np.flatnonzero(((starts[:-1] // C) != ((starts[1:] - 1) // C)) & (counts > 0))
+        crossing = np.flatnonzero(np.logical_or.reduce([(starts[:-1] // C) != ((starts[1:] - 1) // C) for C in Cs])
+                                  & (counts > 0))
         rows = {int(np.argmax(counts))} | set(int(r) for r in rng.choice(nonempty, min(nrand, nonempty.size),
                                                                         replace=False))
         rows |= set(int(r) for r in rng.choice(crossing, min(ncross, crossing.size), replace=False))

@@ -13,7 +13,7 @@ import oracle
 from helpers import DEV, coo_from_arrays, factors_dev, oracle_factors, rel, to_dev, upload
 from paper_1902_03317_amd import synth
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("mttkrp_form")]
 
 TOL_F32 = 1e-5
 TOL_BF16 = 1e-2
@@ -22,16 +22,6 @@ TOL_BF16 = 1e-2
 def api():
     from paper_1902_03317_amd import api as a
     return a
-
-
-@pytest.fixture(autouse=True, params=["run", "wave"])
-def mttkrp_form(request):
-    """Every test of this module runs with both forms of the MTTKRP kernel (each lane group on
-    its own run of nonzeros, or a whole wave on one run)."""
-    from paper_1902_03317_amd._lib import lib
-    lib.pasta_set_mttkrp_form({"run": 1, "wave": 2}[request.param])
-    yield request.param
-    lib.pasta_set_mttkrp_form(0)
 
 
 def check_preprocess(coo, X):
