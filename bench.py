@@ -49,7 +49,12 @@ METRIC = "MTTKRP Gnnz/s + % HBM peak; CP grad step ms, BF16 vs FP32 at stated er
 HBM_PEAK_GBPS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1902_03317_amd", "csrc", f)
                   for f in ("kernels_order.hip", "common.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mttkrp_seg_zipf50M_r32_traffic.json")
+KERNEL_NAMES = {1: "mttkrp_seg_kernel", 2: "mttkrp_wave_kernel"}  # by the form the library reports
+
+
+def traffic_file(kernel: str) -> str:
+    """The committed FETCH_SIZE / WRITE_SIZE summary of a main MTTKRP kernel on the headline tensor."""
+    return os.path.join(ROOT, "profiles", kernel.replace("_kernel", "") + "_zipf50M_r32_traffic.json")
 
 
 # --------------------------------------------------------------------------------------
@@ -268,6 +273,9 @@ def main():
     s_ptr = ctypes.c_void_p(stream)
     from paper_1902_03317_amd._lib import lib as plib
 
+    form = ctypes.c_int(0)
+    forms = [0] * N  # which main kernel each mode's MTTKRP launched
+
     def one_step(rec):
         nonlocal X
         ev = [hip.event() for _ in range(6)]
@@ -282,6 +290,8 @@ def main():
             hip.record(cev[n][0], s_ptr)
             api.mttkrp(X, Ud, n, out=outs[n], workspace=ws_m)
             hip.record(cev[n][1], s_ptr)
+            plib.pasta_last_mttkrp_form(ctypes.byref(form))
+            forms[n] = form.value
         hip.record(ev[2], s_ptr)
         losses = {}
         if do_cp:
@@ -333,10 +343,12 @@ def main():
     kern_ms = [sum(k) / len(k) for k in kern]
     alg_bytes = [bytes_alg(N, R, sf, M, coo.dims[n]) for n in range(N)]
     achieved = sum(alg_bytes) / (sum(kern_ms) * 1e-3) / 1e9  # GB/s over the launches of all modes
+    kernel = KERNEL_NAMES.get(forms[0], "?") if len(set(forms)) == 1 else [KERNEL_NAMES.get(f, "?") for f in forms]
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == spec.name:
+    if isinstance(kernel, str) and os.path.exists(traffic_file(kernel)):
+        tr = json.load(open(traffic_file(kernel)))
+        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == spec.name
+                and kernel in tr.get("kernel", "") and tr.get("factor_dtype") == args.factor_dtype):
             traffic = tr.get("bytes_per_launch")
     ms_step = wall * 1e3 / args.steps
     # achievable streaming bandwidth on this device: a plain 1 GiB device-to-device copy
@@ -371,7 +383,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "copy_gbps": round(copy_gbps, 1),
-                     "kernel": "mttkrp_seg_kernel", "bytes_per_nnz": bytes_alg_per_nnz(N, R, sf),
+                     "kernel": kernel, "bytes_per_nnz": bytes_alg_per_nnz(N, R, sf),
                      "launch_ms": [round(k, 4) for k in kern_ms]},
         "breakdown_ms": {"preprocess": round(sum(pre) / len(pre), 4), "mttkrp_all_modes": round(t_modes, 4),
                          "mttkrp_per_mode": [round(sum(c) / len(c), 4) for c in call],

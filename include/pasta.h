@@ -206,6 +206,12 @@ pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop);
  * tuning and tests; not thread-safe against concurrent calls. */
 pasta_status pasta_set_mttkrp_form(int form);
 
+/* *form = the form (1 = run, 2 = wave-run) of the main kernel that the most
+ * recent MTTKRP-based call with nnz > 0 launched in this process, 0 if there
+ * was none: which kernel a timing taken with pasta_arm_kernel_events measured.
+ * Not thread-safe against concurrent calls. */
+pasta_status pasta_last_mttkrp_form(int *form);
+
 /* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
  * derivative held on the device (no host round trip). */
 pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream);

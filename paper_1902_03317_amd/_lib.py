@@ -50,6 +50,7 @@ SIGNATURES = {
     "pasta_scale_f32": [P, U64, P, P],
     "pasta_arm_kernel_events": [P, P],
     "pasta_set_mttkrp_form": [ctypes.c_int],
+    "pasta_last_mttkrp_form": [P],
     "pasta_cp_als_workspace_bytes": [P, U32, ctypes.POINTER(SZ)],
     "pasta_cp_als_sweep": [P, P, U32, U32, P, P, P, P, SZ, P],
     "pasta_adam_step": [P, P, P, P, P, U64, F32, F32, F32, F32, U32, P],

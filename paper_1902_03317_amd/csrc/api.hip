@@ -65,6 +65,7 @@ constexpr uint32_t kSampleTilesPerWave = 16;
 constexpr uint32_t kWaveChunk = 2048;    // nonzeros per chunk of the wave-run form
 constexpr uint64_t kWaveMinRowLen = 32;  // average nonzeros per row from which it is chosen
 int g_mttkrp_form = 0;                   // 0 automatic, 1 run form, 2 wave-run form
+int g_last_form = 0;                     // form of the most recent MTTKRP main-kernel launch
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -317,6 +318,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     KernelShape s;
     if (!segmented_shape(dt, rank, ldf, ldo, fl, nf, out, max_dim(X), s)) return PASTA_EUNSUPPORTED;
     const bool wave = use_wave(s, X->nnz, X->dims[mode]);
+    if (X->nnz > 0) g_last_form = wave ? 2 : 1;
     MttkrpPlan p;
     if (!plan_mttkrp(X->nnz, rank, s, p, wave)) return PASTA_EUNSUPPORTED;
     if (p.part_bytes > 0 && (work == nullptr || work_bytes < p.part_bytes || ((uintptr_t)work % kAlign) != 0))
@@ -921,6 +923,13 @@ pasta_status pasta_set_mttkrp_form(int form)
 {
     if (form < 0 || form > 2) return PASTA_EINVAL;
     g_mttkrp_form = form;
+    return PASTA_OK;
+}
+
+pasta_status pasta_last_mttkrp_form(int *form)
+{
+    if (!form) return PASTA_EINVAL;
+    *form = g_last_form;
     return PASTA_OK;
 }
 

@@ -242,6 +242,20 @@ def test_deterministic_and_stream_ordered():
     assert torch.equal(a, b)
 
 
+def test_forced_form_is_the_one_launched(mttkrp_form):
+    import ctypes
+    from paper_1902_03317_amd._lib import lib
+    sp, coo = small_zipf(nnz=50_000)
+    X = upload(coo)
+    fd = factors_dev(synth.make_factors(sp))
+    f = ctypes.c_int(-1)
+    for n in range(coo.order):
+        api().mttkrp(X, fd, n)
+        assert lib.pasta_last_mttkrp_form(ctypes.byref(f)) == 0
+        assert f.value == {"run": 1, "wave": 2}[mttkrp_form]
+    assert lib.pasta_last_mttkrp_form(None) != 0
+
+
 def test_values_override_and_alpha():
     sp, coo = small_zipf(nnz=100_000)
     X = upload(coo)
