@@ -160,7 +160,7 @@ struct MttkrpLaunch {
     uint32_t sub;                    // nonzeros per group per chunk (wave form: per chunk)
     uint32_t nchunks;
     float alpha;
-    bool wave;                       // the wave-run form (plain MTTKRP, contiguous shapes)
+    bool wave;                       // the wave-run form (contiguous shapes)
 };
 
 struct SampleLaunch {
@@ -254,6 +254,17 @@ hipError_t launch_fit(const float *M, uint32_t ldm, const float *U, uint32_t ldu
                       uint32_t R, const float *grams, uint32_t order, double *inner_partial,
                       const double *xnorm2, double *fit, hipStream_t st);
 hipError_t launch_sumsq(const float *x, uint64_t n, double *partial, uint32_t nparts, double *out, hipStream_t st);
+
+// Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
+// b % 8). This renumbering gives each XCD one contiguous run of logical
+// indices (a bijection on [0, nblocks)), so neighbouring pieces of work share
+// that XCD's own L2.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t x = b % 8, i = b / 8;
+    const uint32_t q = nblocks / 8, r = nblocks % 8;
+    return x * q + (x < r ? x : r) + i;
+}
 
 constexpr uint32_t kSortThreads = 256;
 constexpr uint32_t kSortItems = 16;

@@ -60,19 +60,14 @@ __device__ __forceinline__ T stream_load(const T *p)
     return *p;
 }
 
-// Chunk handled by a wave. Workgroups are dealt round-robin to the 8 XCDs
-// (workgroup b runs on XCD b % 8); renumbering them so that each XCD takes one
-// contiguous run of chunks keeps the factor rows a run touches in that XCD's
-// own L2.
+// Chunk handled by a wave: each XCD takes one contiguous run of chunks, which
+// keeps the factor rows a run touches in that XCD's own L2.
 __device__ __forceinline__ uint32_t chunk_of_wave(uint32_t nblocks)
 {
 #ifdef PASTA_NO_XCD_REMAP
     return blockIdx.x * 4 + (threadIdx.x >> 6);
 #else
-    const uint32_t b = blockIdx.x, x = b % 8, i = b / 8;
-    const uint32_t q = nblocks / 8, r = nblocks % 8;
-    const uint32_t logical = x * q + (x < r ? x : r) + i;
-    return logical * 4 + (threadIdx.x >> 6);
+    return xcd_contiguous(blockIdx.x, nblocks) * 4 + (threadIdx.x >> 6);
 #endif
 }
 

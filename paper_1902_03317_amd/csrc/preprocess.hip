@@ -239,7 +239,10 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t lds4[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    // neighbouring tiles fill neighbouring pieces of each digit's output run:
+    // on one XCD, their partial cache lines meet in the same L2
+    const uint32_t tile = xcd_contiguous(blockIdx.x, ntiles);
+    const uint64_t base = (uint64_t)tile * kSortTile;
     const uint32_t tile_n = (uint32_t)(n - base < kSortTile ? n - base : kSortTile);
     const uint32_t wbase = (uint32_t)wave * kQuarter + (uint32_t)lane;  // + 64 * r: this lane's r-th key
 
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint32_t *__re
     // this tile's digit counts from the scanned histogram (digit-major, exclusive)
     {
         const uint32_t d = threadIdx.x;
-        const uint64_t j = (uint64_t)d * ntiles + blockIdx.x;
+        const uint64_t j = (uint64_t)d * ntiles + tile;
         const uint64_t last = (uint64_t)kRadix * ntiles - 1;
         const uint32_t g0 = offsets[j];
         const uint32_t cnt = (j < last ? offsets[j + 1] : (uint32_t)n) - g0;
