@@ -364,8 +364,11 @@ template <typename FT, int VEC, int L, bool FUSED, bool OVR>
 __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;                 // nonzeros per step
-    constexpr int US = L < kStep ? L : kStep;    // steps whose gathers go out together
-    constexpr int MS = L / US;                   // such groups of steps per tile of 64 entries
+    // steps whose gathers go out together (fewer when fused, whose extra registers
+    // would otherwise cost a wave per SIMD), and such groups per tile of 64 entries
+    constexpr int US_MAX = FUSED && kStep > 4 ? 4 : kStep;
+    constexpr int US = L < US_MAX ? L : US_MAX;
+    constexpr int MS = L / US;
     using S = Slice<FT, VEC, false>;
     using Packed = typename S::Packed;
     const int lane = threadIdx.x & 63;
