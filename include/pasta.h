@@ -197,7 +197,7 @@ pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop);
 
 /* Which form of the MTTKRP kernel the MTTKRP-based calls run,
  * for every later call in the process: 0 = automatic (the default: the
- * wave-run form when rows average at least 32 nonzeros, else the run form),
+ * wave-run form when rows average at least 48 nonzeros, else the run form),
  * 1 = the run form (each lane group walks its own run of nonzeros), 2 = the
  * wave-run form (a wave walks one run, its groups taking consecutive
  * nonzeros). Both give the same results to rounding; it applies to

@@ -63,7 +63,7 @@ constexpr size_t kAlign = 256;
 constexpr uint32_t kSub = PASTA_SUB;      // nonzeros per lane group per chunk
 constexpr uint32_t kSampleTilesPerWave = 16;
 constexpr uint32_t kWaveChunk = 2048;    // nonzeros per chunk of the wave-run form
-constexpr uint64_t kWaveMinRowLen = 32;  // average nonzeros per row from which it is chosen
+constexpr uint64_t kWaveMinRowLen = 48;  // average nonzeros per row from which it is chosen
 int g_mttkrp_form = 0;                   // 0 automatic, 1 run form, 2 wave-run form
 int g_last_form = 0;                     // form of the most recent MTTKRP main-kernel launch
 
