@@ -72,17 +72,25 @@ def test_cp_grad_fused(dtype):
             assert rel(grads[n].cpu().numpy(), wg32[n]) <= 1e-2
 
 
-def test_cp_grad_order5_and_residual_path_agree():
-    sp = synth.CONFIGS[5].scaled(200_000, dims=(50_000, 50_000, 5000, 1000, 100))
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("order", [4, 5])
+def test_cp_grad_orders_4_5_and_residual_path_agree(order, dtype):
+    """R = 64 at orders 4 and 5 (each has its own gather-group size in the fused kernel):
+    the fused gradient and the residual-weighted MTTKRP against the oracle."""
+    if order == 5:
+        sp = synth.CONFIGS[5].scaled(200_000, dims=(50_000, 50_000, 5000, 1000, 100))
+    else:
+        sp = synth.CONFIGS[3].scaled(200_000, dims=(20_000, 5000, 1000, 200))
     coo = synth.make_coo(sp)
     X = upload(coo)
-    U = synth.make_factors(sp, rank=64, scale=synth.cp_planted_scale(64, 5))
-    fd = factors_dev(U)
+    U = synth.make_factors(sp, rank=64, scale=synth.cp_planted_scale(64, order))
+    fd = factors_dev(U, dtype)
     loss, grads = api().cp_grad(X, fd)
-    wl, wg = oracle.cp_grad(coo.dims, coo.inds, coo.vals, oracle_factors(U), "priv")
+    U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
+    wl, wg = oracle.cp_grad(coo.dims, coo.inds, coo.vals, U64, "priv")
     assert abs(loss.item() - wl) <= 1e-5 * wl
     resid, _ = api().cp_residual_loss(X, fd)
-    for n in range(5):
+    for n in range(order):
         assert rel(grads[n].cpu().numpy(), wg[n]) <= 1e-5
         g2 = api().mttkrp(X, fd, n, vals=resid).cpu().numpy()
         assert rel(g2, wg[n]) <= 1e-5
