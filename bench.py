@@ -26,7 +26,13 @@ The roofline object prices the MTTKRP main kernel against the 8 TB/s HBM
 peak under the algorithmic bytes model B = (4N + 4 + (N-1) R s_f) bytes per
 nonzero + 4 R I_n per launch (Table 2's MTTKRP memory access for order N,
 with the output row written once per row). The kernel's duration is taken
-from HIP events recorded on its own stream around its launch.
+from HIP events recorded on its own stream around its launch. `traffic` is
+that kernel's fabric bytes per launch as rocprofv3 measured them (FETCH_SIZE
+and WRITE_SIZE, each scaled by what it reads for a plain device copy), taken
+from profiles/ while the kernel sources are the ones it was measured on;
+traffic_gbps and traffic_frac put it over the same launch time. The library
+reports which MTTKRP kernel ran (the wave-run form on long rows, else the run
+form); --mttkrp-form forces one.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -382,6 +388,10 @@ def main():
                    "values": spec.values, "seed": spec.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     # the measured fabric bytes per launch over the same launch time
+                     "traffic_gbps": round(traffic / (sum(kern_ms) / N * 1e-3) / 1e9, 1) if traffic else None,
+                     "traffic_frac": round(traffic / (sum(kern_ms) / N * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                     if traffic else None,
                      "copy_gbps": round(copy_gbps, 1),
                      "kernel": kernel, "bytes_per_nnz": bytes_alg_per_nnz(N, R, sf),
                      "launch_ms": [round(k, 4) for k in kern_ms]},
