@@ -136,6 +136,24 @@ __device__ __forceinline__ void store_slice(float *__restrict__ row, int j, uint
     }
 }
 
+// The same with non-temporal stores (contiguous slices), for outputs written
+// once and too large to stay in cache: TTM's fiber rows, MTTKRP on many short rows.
+template <int VEC, bool STRIDED>
+__device__ __forceinline__ void store_slice_nt(float *__restrict__ row, int j, uint32_t R, const float (&v)[VEC],
+                                               float alpha)
+{
+    if constexpr (STRIDED) {
+        store_slice<VEC, STRIDED>(row, j, R, v, alpha);
+    } else {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int e = 0; e < VEC; e += 4) {
+            const f4 t = {alpha * v[e], alpha * v[e + 1], alpha * v[e + 2], alpha * v[e + 3]};
+            __builtin_nontemporal_store(t, reinterpret_cast<f4 *>(row + j * VEC + e));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launch interfaces (host side). Every pointer is device memory.
 // ---------------------------------------------------------------------------

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
                         hrow = cur;
                         multi = true;
                     } else if (lane_on) {  // a row inside the run: complete, store it
-                        store_slice<VEC, STRIDED>(a.out + (uint64_t)cur * a.ldo, j, a.rank, acc, a.alpha);
+                        store_slice_nt<VEC, STRIDED>(a.out + (uint64_t)cur * a.ldo, j, a.rank, acc, a.alpha);
                     }
                 }
                 cur = ru;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
         else if (r == clast && after)
             store_slice<VEC, STRIDED>(a.part + (uint64_t)(2 * (uint64_t)chunk + 1) * a.ldp, j, a.rank, v, 1.0f);
         else
-            store_slice<VEC, STRIDED>(a.out + (uint64_t)r * a.ldo, j, a.rank, v, a.alpha);
+            store_slice_nt<VEC, STRIDED>(a.out + (uint64_t)r * a.ldo, j, a.rank, v, a.alpha);
     };
     if (multi) {  // first row closed inside this run; add what earlier runs carried
         if (cont) {
