@@ -346,6 +346,15 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     }
 }
 
+// Steps per gather group of the fused wave-run kernel. Its residual needs more
+// registers than plain MTTKRP, and fewer gathers in flight buy back a wave per
+// SIMD where that pays (measured at R = 32 and 64: bf16 at order 3 and every
+// dtype at orders 5+ go from 3 to 4 or from 2 to 3 waves; the rest keep theirs).
+constexpr int fused_group_steps(bool bf16)
+{
+    return NM1 <= 2 ? (bf16 ? 2 : 4) : (NM1 == 3 ? 4 : 2);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-run form, for streams whose rows are long. A wave owns one chunk of
 // `sub` consecutive nonzeros and walks it G at a time: in each step, group g
@@ -360,15 +369,6 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 // tiles ahead are loaded behind them. Rows crossing the chunk's edges leave
 // partials in the same slots as the run form, for the same fixup.
 // ---------------------------------------------------------------------------
-// Steps per gather group of the fused wave-run kernel. Its residual needs more
-// registers than plain MTTKRP, and fewer gathers in flight buy back a wave per
-// SIMD where that pays (measured at R = 32 and 64: bf16 at order 3 and every
-// dtype at orders 5+ go from 3 to 4 or from 2 to 3 waves; the rest keep theirs).
-constexpr int fused_group_steps(bool bf16)
-{
-    return NM1 <= 2 ? (bf16 ? 2 : 4) : (NM1 == 3 ? 4 : 2);
-}
-
 template <typename FT, int VEC, int L, bool FUSED, bool OVR>
 __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
