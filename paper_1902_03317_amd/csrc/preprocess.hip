@@ -194,10 +194,16 @@ __global__ __launch_bounds__(256) void radix_hist_kernel(const uint32_t *__restr
     for (uint32_t d = threadIdx.x; d < 4 * kRadix; d += 256) (&cnt[0][0])[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+    uint32_t key[kSortItems];  // every load goes out before the first count
+#pragma unroll
     for (uint32_t i = 0; i < kSortItems; ++i) {
         const uint64_t idx = base + (uint64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&cnt[wave][(keys[idx] >> shift) & (kRadix - 1)], 1u);
+        key[i] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kSortItems; ++i) {
+        const uint64_t idx = base + (uint64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[wave][(key[i] >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     for (uint32_t d = threadIdx.x; d < kRadix; d += 256)
