@@ -40,12 +40,24 @@ struct IndexPtrs {
     uint64_t dim[kMaxOrder];
 };
 
-// flag |= 1 if any coordinate is outside its dimension.
+// flag |= 1 if any coordinate is outside its dimension. Each thread checks
+// four positions of the grid-stride walk at a time, their loads issued together.
 __global__ void validate_kernel(IndexPtrs ip, uint32_t order, uint64_t nnz, uint32_t *flag)
 {
     uint32_t bad = 0;
-    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nnz; m += (uint64_t)gridDim.x * blockDim.x)
-        for (uint32_t k = 0; k < order; ++k) bad |= (uint64_t)ip.p[k][m] >= ip.dim[k];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nnz; m += 4 * stride) {
+        for (uint32_t k = 0; k < order; ++k) {
+            uint32_t v[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint64_t q = m + (uint64_t)t * stride;
+                v[t] = q < nnz ? ip.p[k][q] : 0u;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) bad |= (uint64_t)v[t] >= ip.dim[k];
+        }
+    }
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
 }
 
