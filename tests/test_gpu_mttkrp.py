@@ -249,10 +249,17 @@ def test_forced_form_is_the_one_launched(mttkrp_form):
     X = upload(coo)
     fd = factors_dev(synth.make_factors(sp))
     f = ctypes.c_int(-1)
+    want = {"run": 1, "wave": 2}[mttkrp_form]
+    w = to_dev(np.ones(coo.nnz, np.float32))
     for n in range(coo.order):
-        api().mttkrp(X, fd, n)
-        assert lib.pasta_last_mttkrp_form(ctypes.byref(f)) == 0
-        assert f.value == {"run": 1, "wave": 2}[mttkrp_form]
+        for call in (lambda: api().mttkrp(X, fd, n), lambda: api().mttkrp(X, fd, n, vals=w)):
+            f.value = -1
+            call()
+            assert lib.pasta_last_mttkrp_form(ctypes.byref(f)) == 0
+            assert f.value == want
+    f.value = -1
+    api().cp_grad(X, fd)  # the fused gradient
+    assert lib.pasta_last_mttkrp_form(ctypes.byref(f)) == 0 and f.value == want
     assert lib.pasta_last_mttkrp_form(None) != 0
 
 
