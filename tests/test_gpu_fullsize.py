@@ -291,3 +291,46 @@ def test_order5_full_size_all_ones_marginals(order5):
         got = api.mttkrp(X, ones, n).cpu().numpy().astype(np.float64)
         marg = np.bincount(coo.inds[n], weights=coo.vals.astype(np.float64), minlength=coo.dims[n])
         assert rel(got, np.repeat(marg[:, None], 4, axis=1)) <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_order5_full_size_cp_grad(order5, dtype):
+    """The fused CP gradient on the 200M-nonzero order-5 tensor (R = 64): its loss equals the
+    separately computed residual loss, sampled residuals match the oracle, and sampled gradient
+    rows (rows of at most 1M nonzeros, random and chunk-edge-crossing) match the oracle's
+    residual-weighted MTTKRP of that row's nonzeros."""
+    spec, coo, X = order5
+    from paper_1902_03317_amd import api
+    U = synth.make_factors(spec)
+    fd = factors_dev(U, dtype)
+    U64 = oracle_factors(U, bf16=dtype == torch.bfloat16)
+    loss, grads = api.cp_grad(X, fd)
+    resid, loss_r = api.cp_residual_loss(X, fd)
+    assert abs(loss.item() - loss_r.item()) <= 1e-5 * loss_r.item()
+    rng = np.random.default_rng(61 if dtype == torch.float32 else 62)
+    pick = rng.choice(coo.nnz, 100_000, replace=False)
+    _, want_res = oracle.cp_loss(coo.dims, coo.inds[:, pick], coo.vals[pick], U64)
+    assert rel(resid.cpu().numpy()[pick].astype(np.float64), want_res) <= 1e-5
+    del resid
+    lanes = max(1, spec.rank * (2 if dtype == torch.bfloat16 else 4) // 16)
+    Cs = (256 * (64 // lanes), 2048)
+    for n in range(coo.order):
+        got = grads[n].cpu().numpy().astype(np.float64)
+        counts = np.bincount(coo.inds[n], minlength=coo.dims[n])
+        starts = np.concatenate([[0], np.cumsum(counts)])
+        ok = (counts > 0) & (counts <= 1_000_000)
+        crossing = np.flatnonzero(np.logical_or.reduce([(starts[:-1] // C) != ((starts[1:] - 1) // C) for C in Cs])
+                                  & ok)
+        cand = np.flatnonzero(ok)
+        rows = set(int(r) for r in rng.choice(cand, min(3, cand.size), replace=False))
+        rows |= set(int(r) for r in rng.choice(crossing, min(2, crossing.size), replace=False))
+        for r in sorted(rows):
+            sel = np.flatnonzero(coo.inds[n] == r)
+            _, res = oracle.cp_loss(coo.dims, coo.inds[:, sel], coo.vals[sel], U64)
+            inds = coo.inds[:, sel].copy()
+            inds[n] = 0
+            dims = list(coo.dims)
+            dims[n] = 1
+            want = oracle.mttkrp(dims, inds, res, U64, n)[0]
+            assert rel(got[r], want) <= 1e-5, f"mode {n} row {r} ({counts[r]} nonzeros)"
+        del got
