@@ -52,10 +52,18 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const float *__restri
 // G[p] = sum_b partial[b][p]
 __global__ void gram_finish_kernel(const float *__restrict__ partial, uint32_t nb, uint32_t RR, float *__restrict__ G)
 {
+    // eight interleaved running sums over the blocks, so eight loads are in
+    // flight; added in a fixed order (deterministic)
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < RR; p += gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        for (uint32_t b = 0; b < nb; ++b) s += partial[(uint64_t)b * RR + p];
-        G[p] = s;
+        float acc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = 0.0f;
+        for (uint32_t b = 0; b < nb; b += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                acc[k] += b + k < nb ? partial[(uint64_t)(b + k) * RR + p] : 0.0f;
+        }
+        G[p] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     }
 }
 

@@ -687,9 +687,20 @@ hipError_t launch_zero_rows(float *out, uint32_t nrows, uint32_t ldo, uint32_t r
 // Deterministic sum of n fp64 partials by one block (fixed tree order).
 __global__ __launch_bounds__(256) void sum_f64_kernel(const double *part, uint32_t n, double *out)
 {
+    // eight interleaved running sums per thread, so eight loads are in flight;
+    // they are added in a fixed order, so the result stays deterministic
     __shared__ double lds[4];
-    double s = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256) s += part[i];
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256 * 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t q = i + 256u * k;
+            acc[k] += q < n ? part[q] : 0.0;
+        }
+    }
+    double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     s = wave_sum_f64(s);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
     __syncthreads();
