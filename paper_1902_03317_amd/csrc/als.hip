@@ -67,54 +67,46 @@ __global__ void gram_finish_kernel(const float *__restrict__ partial, uint32_t n
     }
 }
 
-// One workgroup: V = Hadamard of the Grams of every mode but n, its Cholesky
-// factor V = L L^T, then Vinv = V^{-1}. flag |= 1 if V is not positive definite.
+// One workgroup: V = Hadamard of the Grams of every mode but n, then
+// Vinv = V^{-1} by Gauss-Jordan elimination on [V | I] without pivoting (V is
+// symmetric positive definite: its pivots are the Schur-complement diagonals,
+// the squared diagonal of its Cholesky factor). Thread t works on columns
+// t % 64 (+ 64) and rows t / 64 (+ 4k) of the augmented matrix in LDS, so no
+// index needs a division. flag |= 1 if a pivot is not positive (V not
+// numerically positive definite).
 __global__ __launch_bounds__(256) void als_solve_kernel(const float *__restrict__ grams, uint32_t order,
                                                         uint32_t mode, uint32_t R, float *__restrict__ Vinv,
                                                         uint32_t *__restrict__ flag)
 {
-    __shared__ float V[kAlsMaxRank][kAlsMaxRank + 1];
-    __shared__ float W[kAlsMaxRank][kAlsMaxRank + 1];  // L^{-1}
-    const uint32_t RR = R * R;
-    for (uint32_t p = threadIdx.x; p < RR; p += blockDim.x) {
-        float v = 1.0f;
-        for (uint32_t k = 0; k < order; ++k)
-            if (k != mode) v *= grams[(uint64_t)k * RR + p];
-        V[p / R][p % R] = v;
-    }
+    __shared__ float A[kAlsMaxRank][2 * kAlsMaxRank + 1];
+    __shared__ float F[kAlsMaxRank];
+    const uint32_t RR = R * R, W2 = 2 * R, cl = threadIdx.x & 63, rb = threadIdx.x >> 6;
+    for (uint32_t i = rb; i < R; i += 4)
+        for (uint32_t c = cl; c < R; c += 64) {
+            float v = 1.0f;
+            for (uint32_t k = 0; k < order; ++k)
+                if (k != mode) v *= grams[(uint64_t)k * RR + i * R + c];
+            A[i][c] = v;
+            A[i][R + c] = i == c ? 1.0f : 0.0f;
+        }
     __syncthreads();
-    // Cholesky, column by column (right-looking); R <= 64 so one column per step
     for (uint32_t j = 0; j < R; ++j) {
-        if (threadIdx.x == 0) {
-            const float d = V[j][j];
-            if (!(d > 0.0f)) atomicOr(flag, 1u);
-            V[j][j] = d > 0.0f ? sqrtf(d) : 1.0f;
-        }
+        const float piv = A[j][j];  // read by every thread before row j changes
+        if (threadIdx.x == 0 && !(piv > 0.0f)) atomicOr(flag, 1u);
+        const float inv = piv > 0.0f ? 1.0f / piv : 1.0f;
+        for (uint32_t i = threadIdx.x; i < R; i += blockDim.x) F[i] = A[i][j];
         __syncthreads();
-        for (uint32_t i = j + 1 + threadIdx.x; i < R; i += blockDim.x) V[i][j] /= V[j][j];
+        for (uint32_t c = threadIdx.x; c < W2; c += blockDim.x) A[j][c] *= inv;
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < (R - j - 1) * (R - j - 1); p += blockDim.x) {
-            const uint32_t i = j + 1 + p / (R - j - 1), c = j + 1 + p % (R - j - 1);
-            if (c <= i) V[i][c] -= V[i][j] * V[c][j];
+        for (uint32_t c = cl; c < W2; c += 64) {
+            const float rj = A[j][c];
+            for (uint32_t i = rb; i < R; i += 4)
+                if (i != j) A[i][c] -= F[i] * rj;
         }
         __syncthreads();
     }
-    // W = L^{-1}: forward substitution, one column of W per thread
-    for (uint32_t c = threadIdx.x; c < R; c += blockDim.x) {
-        for (uint32_t i = 0; i < R; ++i) {
-            float s = i == c ? 1.0f : 0.0f;
-            for (uint32_t k = c; k < i; ++k) s -= V[i][k] * W[k][c];
-            W[i][c] = i < c ? 0.0f : s / V[i][i];
-        }
-    }
-    __syncthreads();
-    // Vinv = W^T W
-    for (uint32_t p = threadIdx.x; p < RR; p += blockDim.x) {
-        const uint32_t a = p / R, b = p % R;
-        float s = 0.0f;
-        for (uint32_t k = (a > b ? a : b); k < R; ++k) s += W[k][a] * W[k][b];
-        Vinv[p] = s;
-    }
+    for (uint32_t i = rb; i < R; i += 4)
+        for (uint32_t c = cl; c < R; c += 64) Vinv[i * R + c] = A[i][R + c];
 }
 
 // U[i, :] = M[i, :] Vinv (row by row; Vinv staged in LDS)
@@ -224,10 +216,26 @@ __global__ __launch_bounds__(256) void fit_kernel(const float *__restrict__ gram
 __global__ __launch_bounds__(256) void sumsq_partial_kernel(const float *__restrict__ x, uint64_t n,
                                                             double *__restrict__ partial)
 {
+    // 16-byte loads when the array allows them, four in flight per thread
+    // (interleaved running sums, added in a fixed order); the scalar tail goes
+    // to the first thread
     __shared__ double lds[4];
-    double s = 0.0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        s += (double)x[i] * (double)x[i];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool vec = ((uintptr_t)x % 16) == 0;
+    const uint64_t n4 = vec ? n / 4 : 0;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
+    for (uint64_t i = t0; i < n4; i += 4 * stride) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t q = i + (uint64_t)k * stride;
+            const float4 v = q < n4 ? x4[q] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            acc[k] += ((double)v.x * v.x + (double)v.y * v.y) + ((double)v.z * v.z + (double)v.w * v.w);
+        }
+    }
+    for (uint64_t i = 4 * n4 + t0; i < n; i += stride) acc[0] += (double)x[i] * (double)x[i];
+    double s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     s = wave_sum_f64(s);
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
     __syncthreads();
