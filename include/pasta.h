@@ -212,6 +212,25 @@ pasta_status pasta_set_mttkrp_form(int form);
  * Not thread-safe against concurrent calls. */
 pasta_status pasta_last_mttkrp_form(int *form);
 
+/* Measurement kernel: the gather rate of the vector memory pipeline, the
+ * ceiling the MTTKRP kernels' factor-row gathers are compared with. Launches
+ * `blocks` workgroups of 4 waves; each wave is 64 / lanes groups of `lanes`
+ * lanes, and in each of `steps` steps every group reads one row of
+ * lanes x 16 bytes from d_table (lane j reads bytes 16j .. 16j+15), the row
+ * drawn by a hash of (wave, step, group / share): share = 1 gives every group
+ * its own row, share = 64 / lanes one row per wave. Eight steps' loads are in
+ * flight at a time. Bytes delivered = blocks * 256 * steps * 16.
+ *   d_table  rows * lanes * 16 bytes, 16-byte aligned; rows a power of two
+ *            (the table's size picks the cache level that serves it).
+ *   lanes    4, 8 or 16 (the group widths of the MTTKRP kernels' 16-byte
+ *            slices); share a power of two <= 64 / lanes; steps a multiple
+ *            of 8.
+ *   d_out    blocks * 256 * 16 bytes, 16-byte aligned; receives a fold of
+ *            the loaded words (kept so that no load is dropped).
+ * Asynchronous on `stream`. */
+pasta_status pasta_probe_gather(const void *d_table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t steps,
+                                uint32_t blocks, void *d_out, void *stream);
+
 /* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
  * derivative held on the device (no host round trip). */
 pasta_status pasta_scale_f32(float *d_x, uint64_t count, const double *d_alpha, void *stream);

@@ -34,7 +34,8 @@ def _jobs():
             (os.path.join(CSRC, "preprocess.hip"), "preprocess.o", []),
             (os.path.join(CSRC, "als.hip"), "als.o", []),
             (os.path.join(CSRC, "fibers.hip"), "fibers.o", []),
-            (os.path.join(CSRC, "elementwise.hip"), "elementwise.o", [])]
+            (os.path.join(CSRC, "elementwise.hip"), "elementwise.o", []),
+            (os.path.join(CSRC, "calibrate.hip"), "calibrate.o", [])]
     for n in ORDERS:
         srcs.append((os.path.join(CSRC, "kernels_order.hip"), f"kernels_order{n}.o", [f"-DPASTA_NM1={n - 1}"]))
     return srcs

@@ -206,16 +206,17 @@ def first_distinct(keys: Sequence[np.ndarray], threads: int = 8) -> np.ndarray:
 
 
 def _draw_coords(spec: TensorSpec, gens, count: int, samplers, perms):
-    out = []
-    for k, d in enumerate(spec.dims):
-        g = gens[k]
+    """One batch of coordinates; each mode draws from its own stream, so the modes
+    are drawn in parallel threads with the same result as one after another."""
+    def one(k):
+        d, g = spec.dims[k], gens[k]
         s = spec.zipf[k] if spec.zipf else None
         if s is None:
-            out.append(g.integers(0, d, size=count, dtype=np.int64).astype(np.uint32))
-        else:
-            r = samplers[k].ranks(g.random(count))
-            out.append(perms[k][r])
-    return out
+            return g.integers(0, d, size=count, dtype=np.int64).astype(np.uint32)
+        return perms[k][samplers[k].ranks(g.random(count))]
+
+    with ThreadPoolExecutor(len(spec.dims)) as ex:
+        return list(ex.map(one, range(len(spec.dims))))
 
 
 def make_coo(spec: TensorSpec, threads: int = 8) -> CooTensor:
