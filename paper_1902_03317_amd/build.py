@@ -36,8 +36,13 @@ def _jobs():
             (os.path.join(CSRC, "fibers.hip"), "fibers.o", []),
             (os.path.join(CSRC, "elementwise.hip"), "elementwise.o", []),
             (os.path.join(CSRC, "calibrate.hip"), "calibrate.o", [])]
+    # The wave-run kernel's lambdas update shared register state in both arms of
+    # branches; sinking those stores into one store through a selected pointer
+    # would put that state in private (scratch) memory, so that transform is off.
+    order_flags = ["-mllvm", "-simplifycfg-sink-common=false"]
     for n in ORDERS:
-        srcs.append((os.path.join(CSRC, "kernels_order.hip"), f"kernels_order{n}.o", [f"-DPASTA_NM1={n - 1}"]))
+        srcs.append((os.path.join(CSRC, "kernels_order.hip"), f"kernels_order{n}.o",
+                     [f"-DPASTA_NM1={n - 1}"] + order_flags))
     return srcs
 
 

@@ -326,12 +326,13 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     const auto &md = X->mode[mode];
     MttkrpLaunch l{};
     l.row = md.sinds[mode];
-    uint32_t q = 0;
-    for (uint32_t k = 0; k < X->order; ++k) {
-        if (k == mode) continue;
+    // the other modes in the order of the mode order's keys after i_n: n-1, n-2, ...
+    // (cyclically), so the factors of the second and third keys come first (the wave-run
+    // kernel reuses their rows along runs)
+    for (uint32_t q = 0; q + 1 < X->order; ++q) {
+        const uint32_t k = (mode + X->order - 1 - q) % X->order;
         l.idx[q] = md.sinds[k];
         l.fac[q] = facs[k];
-        ++q;
     }
     l.facn = fused ? facs[mode] : nullptr;
     l.vals = ovr ? ovr : md.svals;

@@ -407,6 +407,15 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     float rowfac[VEC];
     if constexpr (FUSED) load_rowfac(cur, rowfac);
     float loss_run = 0.0f;
+    // Factor 0 is the mode order's second key (the host lists it first). Where a
+    // group of steps stays in the current row and its first and last nonzeros share
+    // the second key's row, all of its nonzeros do (the stream is sorted by
+    // (i_n, second key, ...)): that row is gathered once for the whole group of
+    // steps, and not at all if it is the row already held.
+    uint32_t held = kNoRow;  // wave-uniform: the factor-0 row whose slice `hold` holds
+    Packed hold;
+#pragma unroll
+    for (int w = 0; w < S::kWords; ++w) hold.w[w] = 0u;
 
     // total of row `cur` over every group (plus `extra` from this step), stored by group 0
     auto close_row = [&](const float (&extra)[VEC]) __attribute__((always_inline)) {
@@ -470,35 +479,42 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
         constexpr bool FULLT = decltype(full)::value;
 #pragma unroll
         for (int m = 0; m < MS; ++m) {
-            Packed gp[US][NM1];
+            // gathers of factors kfrom.. for every step of the group
+            auto issue = [&](Packed (&gp)[US][NM1], int kfrom) __attribute__((always_inline)) {
 #pragma unroll
-            for (int u = 0; u < US; ++u) {
-                const int src = (m * US + u) * G + g;
+                for (int u = 0; u < US; ++u) {
+                    const int src = (m * US + u) * G + g;
 #pragma unroll
-                for (int k = 0; k < NM1; ++k) gather(k, (uint32_t)__shfl((int)E.i[k], src), gp[u][k]);
-            }
-            if (m == 0) {
-                __builtin_amdgcn_sched_barrier(0);  // the next loads go out after these gathers
-                resolve(follow);
-                load_tile(base + 2 * (uint64_t)kWave, target);
-            }
-            // the row of the group of steps' last entry decides the path for all of them
-            const uint32_t mlast = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m + 1) * US * G - 1);
-            if (mlast == cur) {  // the common case: every entry is in the current row
+                    for (int k = 0; k < NM1; ++k)
+                        if (k >= kfrom) gather(k, (uint32_t)__shfl((int)E.i[k], src), gp[u][k]);
+                }
+                if (m == 0) {
+                    __builtin_amdgcn_sched_barrier(0);  // the next loads go out after these gathers
+                    resolve(follow);
+                    load_tile(base + 2 * (uint64_t)kWave, target);
+                }
+            };
+            // the Hadamard product of step u's rows, factor 0 from `first`
+            auto product = [&](const Packed &first, const Packed (&gp)[US][NM1], int u, float (&q)[VEC])
+                               __attribute__((always_inline)) {
+                S::unpack(first, q);
+#pragma unroll
+                for (int k = 1; k < NM1; ++k) {
+                    float t[VEC];
+                    S::unpack(gp[u][k], t);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) q[e] *= t[e];
+                }
+            };
+            // every entry of the group of steps is in the current row
+            auto fast = [&](auto prod) __attribute__((always_inline)) {
 #pragma unroll
                 for (int u = 0; u < US; ++u) {
                     const int src = (m * US + u) * G + g;
                     const float vu = __shfl(E.v, src);
                     const bool on = FULLT || base + (uint64_t)src < c1;
                     float q[VEC];
-                    S::unpack(gp[u][0], q);
-#pragma unroll
-                    for (int k = 1; k < NM1; ++k) {
-                        float t[VEC];
-                        S::unpack(gp[u][k], t);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) q[e] *= t[e];
-                    }
+                    prod(u, q);
                     float w = vu;
                     if constexpr (FUSED) {
                         w = residual(rowfac, q, vu);
@@ -512,6 +528,26 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                         for (int e = 0; e < VEC; ++e) acc[e] = on ? acc[e] + w * q[e] : acc[e];
                     }
                 }
+            };
+            // the row of the group of steps' last entry decides the path for all of them
+            const int lfirst = m * US * G, llast = (m + 1) * US * G - 1;
+            const uint32_t mlast = (uint32_t)__builtin_amdgcn_readlane((int)E.r, llast);
+            const uint32_t k0f = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], lfirst);
+            const uint32_t k0l = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], llast);
+            if (mlast == cur && k0f == k0l) {  // one factor-0 row for the whole group of steps
+                if (k0f != held) {  // the only conditional gather, issued before the others
+                    gather(0, k0f, hold);
+                    held = k0f;
+                }
+                Packed gp[US][NM1];
+                issue(gp, 1);
+                fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) { product(hold, gp, u, q); });
+                continue;
+            }
+            Packed gp[US][NM1];
+            issue(gp, 0);
+            if (mlast == cur) {  // the common case: every entry is in the current row
+                fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) { product(gp[u][0], gp, u, q); });
             } else {  // rows end inside this group of steps
 #pragma unroll
                 for (int u = 0; u < US; ++u) {
@@ -520,14 +556,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                     const float vu = __shfl(E.v, src);
                     const bool on = FULLT || base + (uint64_t)src < c1;
                     float q[VEC];
-                    S::unpack(gp[u][0], q);
-#pragma unroll
-                    for (int k = 1; k < NM1; ++k) {
-                        float t[VEC];
-                        S::unpack(gp[u][k], t);
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e) q[e] *= t[e];
-                    }
+                    product(gp[u][0], gp, u, q);
                     float w = vu;
                     if constexpr (FUSED) {  // each group's own row slice of U^(n)
                         float rf[VEC];
