@@ -328,12 +328,15 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     l.row = md.sinds[mode];
     // the other modes in the order of the mode order's keys after i_n: n-1, n-2, ...
     // (cyclically), so the factors of the second and third keys come first (the wave-run
-    // kernel reuses their rows along runs)
+    // kernel reuses their rows along runs). Mode n's order is lexicographic in
+    // (i_n, i_{n-1}, ..., i_0) and then i_{N-1}: mode 0's has one key after i_0 (then
+    // caller position), every other mode's at least two.
     for (uint32_t q = 0; q + 1 < X->order; ++q) {
         const uint32_t k = (mode + X->order - 1 - q) % X->order;
         l.idx[q] = md.sinds[k];
         l.fac[q] = facs[k];
     }
+    l.keys = mode == 0 ? 1u : std::min<uint32_t>(2u, X->order - 1);
     l.facn = fused ? facs[mode] : nullptr;
     l.vals = ovr ? ovr : md.svals;
     l.perm = ovr ? md.perm : nullptr;

@@ -177,6 +177,7 @@ struct MttkrpLaunch {
     uint32_t ldf, ldo, ldp, rank;
     uint32_t sub;                    // nonzeros per group per chunk (wave form: per chunk)
     uint32_t nchunks;
+    uint32_t keys;                   // leading factors whose indices are sort keys of the stream
     float alpha;
     bool wave;                       // the wave-run form (contiguous shapes)
 };

@@ -49,6 +49,7 @@ struct MttkrpArgs {
     uint64_t nnz;
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
     uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
+    uint32_t keys;       // factors 0 .. keys-1 are the stream's sort keys after i_n, in key order
     float alpha;
 };
 
@@ -412,10 +413,13 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     // the second key's row, all of its nonzeros do (the stream is sorted by
     // (i_n, second key, ...)): that row is gathered once for the whole group of
     // steps, and not at all if it is the row already held.
-    uint32_t held = kNoRow;  // wave-uniform: the factor-0 row whose slice `hold` holds
-    Packed hold;
+    // From order 4 on, factor 1 is treated the same way where the group of steps also
+    // shares its row and the stream is sorted by it next (it is the third key: every
+    // mode but mode 0, whose order falls back to caller position after two keys).
+    uint32_t held = kNoRow, held1 = kNoRow;  // wave-uniform: the rows whose slices hold / hold1 hold
+    Packed hold, hold1;
 #pragma unroll
-    for (int w = 0; w < S::kWords; ++w) hold.w[w] = 0u;
+    for (int w = 0; w < S::kWords; ++w) hold.w[w] = hold1.w[w] = 0u;
 
     // total of row `cur` over every group (plus `extra` from this step), stored by group 0
     auto close_row = [&](const float (&extra)[VEC]) __attribute__((always_inline)) {
@@ -494,14 +498,15 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                     load_tile(base + 2 * (uint64_t)kWave, target);
                 }
             };
-            // the Hadamard product of step u's rows, factor 0 from `first`
-            auto product = [&](const Packed &first, const Packed (&gp)[US][NM1], int u, float (&q)[VEC])
-                               __attribute__((always_inline)) {
-                S::unpack(first, q);
+            // the Hadamard product of step u's rows, factor 0 from `f0`, factor 1 from `f1`
+            // when `one` is set, the rest from gp
+            auto product = [&](const Packed &f0, const Packed &f1, bool one, const Packed (&gp)[US][NM1], int u,
+                               float (&q)[VEC]) __attribute__((always_inline)) {
+                S::unpack(f0, q);
 #pragma unroll
                 for (int k = 1; k < NM1; ++k) {
                     float t[VEC];
-                    S::unpack(gp[u][k], t);
+                    S::unpack(k == 1 && one ? f1 : gp[u][k], t);
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) q[e] *= t[e];
                 }
@@ -535,19 +540,42 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
             const uint32_t k0f = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], lfirst);
             const uint32_t k0l = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], llast);
             if (mlast == cur && k0f == k0l) {  // one factor-0 row for the whole group of steps
-                if (k0f != held) {  // the only conditional gather, issued before the others
+                bool one = false;
+                if constexpr (NM1 >= 3) {
+                    one = a.keys >= 2 && __builtin_amdgcn_readlane((int)E.i[1], lfirst) ==
+                                             __builtin_amdgcn_readlane((int)E.i[1], llast);
+                }
+                // the conditional gathers go out before the others, so the counted waits
+                // for the later loads stay exact
+                if (k0f != held) {
                     gather(0, k0f, hold);
                     held = k0f;
                 }
                 Packed gp[US][NM1];
-                issue(gp, 1);
-                fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) { product(hold, gp, u, q); });
+                if (one) {  // and one factor-1 row
+                    const uint32_t k1f = (uint32_t)__builtin_amdgcn_readlane((int)E.i[1], lfirst);
+                    if (k1f != held1) {
+                        gather(1, k1f, hold1);
+                        held1 = k1f;
+                    }
+                    issue(gp, 2);
+                    fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) {
+                        product(hold, hold1, true, gp, u, q);
+                    });
+                } else {
+                    issue(gp, 1);
+                    fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) {
+                        product(hold, hold1, false, gp, u, q);
+                    });
+                }
                 continue;
             }
             Packed gp[US][NM1];
             issue(gp, 0);
             if (mlast == cur) {  // the common case: every entry is in the current row
-                fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) { product(gp[u][0], gp, u, q); });
+                fast([&](int u, float (&q)[VEC]) __attribute__((always_inline)) {
+                    product(gp[u][0], hold1, false, gp, u, q);
+                });
             } else {  // rows end inside this group of steps
 #pragma unroll
                 for (int u = 0; u < US; ++u) {
@@ -556,7 +584,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                     const float vu = __shfl(E.v, src);
                     const bool on = FULLT || base + (uint64_t)src < c1;
                     float q[VEC];
-                    product(gp[u][0], gp, u, q);
+                    product(gp[u][0], hold1, false, gp, u, q);
                     float w = vu;
                     if constexpr (FUSED) {  // each group's own row slice of U^(n)
                         float rf[VEC];
@@ -876,6 +904,7 @@ hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool 
     a.sub = l.sub;
     a.nchunks = l.nchunks;
     a.row_bytes = l.ldf * (bf16 ? 2u : 4u);
+    a.keys = l.keys;
     a.alpha = l.alpha;
     return dispatch<MttkrpRun>(a, bf16, s, st, fused, l.wave);
 }
