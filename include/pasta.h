@@ -48,7 +48,8 @@ typedef enum {
     PASTA_ERANGE = 2,       /* some coordinate is >= its dimension */
     PASTA_EUNSUPPORTED = 3, /* order, rank, dtype or alignment outside the supported set */
     PASTA_EWORKSPACE = 4,   /* workspace smaller than the queried size, or not 256-byte aligned */
-    PASTA_EHIP = 5          /* a HIP runtime call failed; see pasta_last_hip_error() */
+    PASTA_EHIP = 5,         /* a HIP runtime call failed; see pasta_last_hip_error() */
+    PASTA_EINTERNAL = 6     /* a kernel found the preprocessed tensor inconsistent (pasta_coo_check) */
 } pasta_status;
 
 typedef enum { PASTA_F32 = 0, PASTA_BF16 = 1 } pasta_dtype;
@@ -86,6 +87,15 @@ pasta_status pasta_coo_workspace_bytes(uint32_t order, const uint64_t *dims, uin
 pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz, const uint32_t *const *d_inds,
                               const float *d_vals, void *d_workspace, size_t workspace_bytes, void *stream,
                               pasta_coo **out);
+
+/* Waits for `stream`, then reports whether any MTTKRP-based kernel that ran on X
+ * since pasta_coo_create found its mode-sorted stream out of order (PASTA_EINTERNAL;
+ * their outputs are then undefined) or none did (PASTA_OK). The wave-run MTTKRP
+ * kernel checks the row order it relies on and, instead of looping on a stream that
+ * breaks it, sets a device flag in X's workspace and stops that row walk; the flag
+ * stays set for the life of the handle. A preprocessed tensor is always in order,
+ * so PASTA_EINTERNAL means its workspace was overwritten or a library defect. */
+pasta_status pasta_coo_check(const pasta_coo *X, void *stream);
 
 /* Free the host handle. Device memory stays the caller's. */
 pasta_status pasta_coo_destroy(pasta_coo *X);

@@ -180,18 +180,17 @@ def sort_perm(rows) -> np.ndarray:
 
 
 def mode_orders(inds):
-    """The order of the nonzeros for every mode: mode n's order is the stable sort
-    by i_n of mode n-1's order, starting from mode N-1 sorted stably out of the
-    caller's order. Equivalently, mode n's order is lexicographic in
-    (i_n, i_{n-1}, ..., i_0), then i_{N-1} (for n < N-1), then caller position."""
+    """The order of the nonzeros for every mode: mode n's order is lexicographic in
+    (i_n, i_{n-1}, ..., i_0), then i_{N-1} (for n < N-1), then caller position (each
+    mode's order is the stable sort by i_n of the previous mode's order, mode N-1's
+    coming from the caller's order sorted stably by i_{N-1}). One stable ``np.lexsort``
+    per mode on that key (its last key is the primary one; ties keep caller order)."""
     inds = np.asarray(inds)
     N = inds.shape[0]
-    prev = np.argsort(inds[N - 1], kind="stable")
     out = []
     for n in range(N):
-        o = prev[np.argsort(inds[n][prev], kind="stable")]
-        out.append(o.astype(np.uint32))
-        prev = o
+        key = [inds[k] for k in range(n, -1, -1)] + ([inds[N - 1]] if n < N - 1 else [])
+        out.append(np.lexsort(key[::-1]).astype(np.uint32))
     return out
 
 
@@ -222,26 +221,51 @@ def rel_fro(y, ystar) -> float:
     return num / den if den > 0 else float(np.linalg.norm(y))
 
 
+def cp_als_update(dims, inds, vals, factors, n: int, strategy: str = "seq"):
+    """One mode of a CP-ALS sweep in FP64 (alternating least squares for CPD, Section
+    3.1.1): M = MTTKRP_n, V = Hadamard_{k!=n} U_k^T U_k, U_n = M V^{-1} (a library
+    solve), then the columns of U_n scaled to unit 2-norm (zero columns stay zero).
+    Returns (U_n, lambda = the column norms, M, the 2-norm condition number of V)."""
+    U = [None if f is None else np.asarray(f, dtype=np.float64) for f in factors]
+    M = mttkrp(dims, inds, vals, U, n, strategy)
+    R = M.shape[1]
+    V = np.ones((R, R))
+    for k in range(len(dims)):
+        if k != n:
+            V *= U[k].T @ U[k]
+    Un = np.linalg.solve(V, M.T).T
+    lam = np.linalg.norm(Un, axis=0)
+    return np.where(lam > 0, Un / np.where(lam > 0, lam, 1.0), 0.0), lam, M, float(np.linalg.cond(V))
+
+
+def cp_fit(dims, inds, vals, factors, lam) -> float:
+    """1 - ||X - [[lambda; U]]|| / ||X|| over the full tensor (X zero off the nonzeros),
+    with ||[[lambda; U]]||^2 = lambda^T (Hadamard_k U_k^T U_k) lambda and the inner
+    product taken at the nonzeros (the model's values there, from cp_sample), so the
+    coordinates are taken to be distinct."""
+    U = [np.asarray(f, dtype=np.float64) for f in factors]
+    lam = np.asarray(lam, dtype=np.float64)
+    x = np.asarray(vals, np.float64)
+    x2 = float(x @ x)
+    G = np.ones((lam.size, lam.size))
+    for u in U:
+        G *= u.T @ u
+    model2 = float(lam @ G @ lam)
+    inner = float(x @ cp_sample(dims, inds, [U[0] * lam[None, :]] + U[1:]))
+    return 1.0 - np.sqrt(max(0.0, x2 + model2 - 2.0 * inner)) / np.sqrt(x2) if x2 > 0 else 0.0
+
+
 def cp_als_sweep(dims, inds, vals, factors, strategy: str = "seq"):
-    """One CP-ALS sweep in FP64 (alternating least squares for CPD, Section 3.1.1):
-    for each mode n, U_n = MTTKRP_n (Hadamard_{k!=n} U_k^T U_k)^{-1}, then the columns
-    of U_n are scaled to unit 2-norm (lambda = the norms). Returns (factors, lambda, fit)
-    with fit = 1 - ||X - [[lambda; U]]|| / ||X|| over the full tensor (X zero off the
-    nonzeros), computed from the Gram matrices and the last MTTKRP; ||X||^2 is the sum
-    of the squared values, so the coordinates are taken to be distinct."""
+    """One CP-ALS sweep in FP64: ``cp_als_update`` for modes 0 .. N-1 in turn, each
+    with the factors updated so far. Returns (factors, lambda of the last mode, fit)
+    with fit = 1 - ||X - [[lambda; U]]|| / ||X|| computed from the Gram matrices and
+    the last MTTKRP (<X, model> = sum_r lambda_r <M[:, r], U_{N-1}[:, r]>); ||X||^2
+    is the sum of the squared values, so the coordinates are taken to be distinct."""
     U = [np.array(f, dtype=np.float64) for f in factors]
     N = len(dims)
-    lam = np.ones(U[0].shape[1])
-    M = None
+    lam, M = None, None
     for n in range(N):
-        M = mttkrp(dims, inds, vals, U, n, strategy)
-        V = np.ones((U[0].shape[1],) * 2)
-        for k in range(N):
-            if k != n:
-                V *= U[k].T @ U[k]
-        Un = np.linalg.solve(V, M.T).T
-        lam = np.linalg.norm(Un, axis=0)
-        U[n] = np.where(lam > 0, Un / np.where(lam > 0, lam, 1.0), 0.0)
+        U[n], lam, M, _ = cp_als_update(dims, inds, vals, U, n, strategy)
     x2 = float(np.dot(np.asarray(vals, np.float64), np.asarray(vals, np.float64)))
     G = np.ones((U[0].shape[1],) * 2)
     for k in range(N):

@@ -29,13 +29,14 @@ PASTA_F32 = 0
 PASTA_BF16 = 1
 EWOP = {"add": 0, "sub": 1, "mul": 2, "div": 3}
 STATUS = {0: "PASTA_OK", 1: "PASTA_EINVAL", 2: "PASTA_ERANGE", 3: "PASTA_EUNSUPPORTED", 4: "PASTA_EWORKSPACE",
-          5: "PASTA_EHIP"}
+          5: "PASTA_EHIP", 6: "PASTA_EINTERNAL"}
 
 # name -> argtypes; every entry point returns pasta_status (int)
 SIGNATURES = {
     "pasta_coo_workspace_bytes": [U32, P, U64, ctypes.POINTER(SZ)],
     "pasta_coo_create": [U32, P, U64, P, P, P, SZ, P, ctypes.POINTER(P)],
     "pasta_coo_destroy": [P],
+    "pasta_coo_check": [P, P],
     "pasta_coo_info": [P, ctypes.POINTER(U32), ctypes.POINTER(U64)],
     "pasta_coo_mode_view": [P, U32, ctypes.POINTER(P), ctypes.POINTER(P), P, ctypes.POINTER(P)],
     "pasta_mttkrp_workspace_bytes": [P, U32, U32, ctypes.c_int, ctypes.POINTER(SZ)],

@@ -18,8 +18,15 @@ def _stream(stream=None) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _scratch(nbytes: int, device) -> torch.Tensor:
-    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+def _scratch(nbytes: int, device, stream=None) -> torch.Tensor:
+    """Device scratch for one call. It is allocated while the call's stream is current, so
+    torch's caching allocator hands the block to other work only in that stream's order
+    (a block taken on another stream could be reused while the call's kernels still run)."""
+    n = max(int(nbytes), 256)
+    if stream is None:
+        return torch.empty(n, dtype=torch.uint8, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty(n, dtype=torch.uint8, device=device)
 
 
 class Coo:
@@ -56,7 +63,7 @@ class Coo:
         if workspace is not None and workspace.dtype == torch.uint8 and workspace.numel() >= nbytes.value:
             self.workspace = workspace
         else:
-            self.workspace = _scratch(nbytes.value, self.device)
+            self.workspace = _scratch(nbytes.value, self.device, stream)
         self._ind_ptrs = ptr_array([r.data_ptr() for r in self.inds])
         h = ctypes.c_void_p()
         check(lib.pasta_coo_create(self.order, self._dims_c, self.nnz, self._ind_ptrs, self.vals.data_ptr(),
@@ -68,6 +75,11 @@ class Coo:
     @property
     def handle(self) -> ctypes.c_void_p:
         return self._h
+
+    def check(self, stream=None) -> None:
+        """Wait for the stream and raise if a kernel found this tensor's sorted streams
+        out of order (pasta_coo_check; the affected outputs are undefined)."""
+        check(lib.pasta_coo_check(self._h, _stream(stream)), "pasta_coo_check")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -151,7 +163,8 @@ def mttkrp(X: Coo, factors: Sequence[Optional[torch.Tensor]], mode: int, out: Op
             raise ValueError("vals must be a contiguous float32 tensor of nnz entries")
         vptr = vals.data_ptr()
     if workspace is None:
-        workspace = _scratch(mttkrp_workspace_bytes(X, mode, R, facs[(mode + 1) % X.order].dtype), X.device)
+        workspace = _scratch(mttkrp_workspace_bytes(X, mode, R, facs[(mode + 1) % X.order].dtype), X.device,
+                             stream)
     check(lib.pasta_mttkrp(X.handle, int(mode), ptrs, dt, R, ldf, vptr, float(alpha), out.data_ptr(),
                            int(out.stride(0)), workspace.data_ptr(), workspace.numel(), _stream(stream)),
           "pasta_mttkrp")
@@ -186,7 +199,7 @@ def cp_residual_loss(X: Coo, factors, resid: Optional[torch.Tensor] = None, want
     loss = torch.empty((), dtype=torch.float64, device=X.device)
     n = ctypes.c_size_t()
     check(lib.pasta_cp_workspace_bytes(X.handle, R, dt, ctypes.byref(n)), "pasta_cp_workspace_bytes")
-    ws = _scratch(n.value, X.device)
+    ws = _scratch(n.value, X.device, stream)
     check(lib.pasta_cp_residual_loss(X.handle, ptrs, dt, R, ldf, None if resid is None else resid.data_ptr(),
                                      loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
           "pasta_cp_residual_loss")
@@ -213,7 +226,7 @@ def cp_grad(X: Coo, factors, grads: Optional[List[torch.Tensor]] = None, alpha: 
             raise ValueError("grads must be float32 [dims[n], >=R] sharing one row stride")
     loss = torch.empty((), dtype=torch.float64, device=X.device) if want_loss else None
     if workspace is None:
-        workspace = _scratch(cp_grad_workspace_bytes(X, R, factors[0].dtype), X.device)
+        workspace = _scratch(cp_grad_workspace_bytes(X, R, factors[0].dtype), X.device, stream)
     check(lib.pasta_cp_grad(X.handle, ptrs, dt, R, ldf, float(alpha), ptr_array([g.data_ptr() for g in grads]),
                             ldg, None if loss is None else loss.data_ptr(), workspace.data_ptr(), workspace.numel(),
                             _stream(stream)), "pasta_cp_grad")
@@ -247,7 +260,7 @@ def cp_als_sweep(X: Coo, factors: List[torch.Tensor], lam: Optional[torch.Tensor
     if workspace is None:
         n = ctypes.c_size_t()
         check(lib.pasta_cp_als_workspace_bytes(X.handle, R, ctypes.byref(n)), "pasta_cp_als_workspace_bytes")
-        workspace = _scratch(n.value, X.device)
+        workspace = _scratch(n.value, X.device, stream)
     check(lib.pasta_cp_als_sweep(X.handle, ptrs, R, ldf, lam.data_ptr(), None if fit is None else fit.data_ptr(),
                                  info.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream)),
           "pasta_cp_als_sweep")
@@ -274,7 +287,7 @@ class Fibers:
         if workspace is not None and workspace.dtype == torch.uint8 and workspace.numel() >= nbytes.value:
             self.workspace = workspace
         else:
-            self.workspace = _scratch(nbytes.value, self.device)
+            self.workspace = _scratch(nbytes.value, self.device, stream)
         h = ctypes.c_void_p()
         check(lib.pasta_fibers_create(X.handle, self.mode, self.workspace.data_ptr(), self.workspace.numel(),
                                       _stream(stream), ctypes.byref(h)), "pasta_fibers_create")
@@ -332,7 +345,7 @@ def ttm(F: Fibers, U: torch.Tensor, out: Optional[torch.Tensor] = None, workspac
     if out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != F.nfibs or out.shape[1] < R \
             or out.stride(1) != 1:
         raise ValueError("out must be float32 [nfibs, >= R] with unit column stride")
-    ws = workspace if workspace is not None else _scratch(ttm_workspace_bytes(F, R, U.dtype), F.device)
+    ws = workspace if workspace is not None else _scratch(ttm_workspace_bytes(F, R, U.dtype), F.device, stream)
     check(lib.pasta_ttm(F.handle, U.data_ptr(), _DT[U.dtype], R, ldu, out.data_ptr(),
                         int(max(out.stride(0), out.shape[1])), ws.data_ptr(), ws.numel(), _stream(stream)),
           "pasta_ttm")
@@ -356,7 +369,7 @@ def ttv(F: Fibers, v: torch.Tensor, out: Optional[torch.Tensor] = None, workspac
         out = torch.empty(F.nfibs, dtype=torch.float32, device=F.device)
     if out.dtype != torch.float32 or out.numel() != F.nfibs or not out.is_contiguous():
         raise ValueError("out must be a contiguous float32 [nfibs] tensor")
-    ws = workspace if workspace is not None else _scratch(ttv_workspace_bytes(F), F.device)
+    ws = workspace if workspace is not None else _scratch(ttv_workspace_bytes(F), F.device, stream)
     check(lib.pasta_ttv(F.handle, v.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)),
           "pasta_ttv")
     return out
@@ -415,7 +428,7 @@ def tew(op: str, dims_x: Sequence[int], inds_x: torch.Tensor, vals_x: torch.Tens
     cap = max(nx + ny, 1)
     iz = torch.empty((N, cap), dtype=torch.int32, device=vals_x.device)
     vz = torch.empty(cap, dtype=torch.float32, device=vals_x.device)
-    ws = workspace if workspace is not None else _scratch(tew_workspace_bytes(N, nx, ny), vals_x.device)
+    ws = workspace if workspace is not None else _scratch(tew_workspace_bytes(N, nx, ny), vals_x.device, stream)
     dx = (ctypes.c_uint64 * N)(*[int(d) for d in dims_x])
     dy = (ctypes.c_uint64 * N)(*[int(d) for d in dims_y])
     dz = (ctypes.c_uint64 * N)()

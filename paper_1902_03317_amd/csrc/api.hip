@@ -18,6 +18,8 @@ struct pasta_coo {
     uint64_t dims[kMaxOrder];
     const uint32_t *inds[kMaxOrder];  // caller order (caller-owned)
     const float *vals;
+    uint32_t *flag;  // device word in the workspace: 0 after a good index check; kernels set
+                     // it to 2 if they find the preprocessed stream inconsistent (sticky)
     struct Mode {
         uint32_t *sinds[kMaxOrder];  // sorted copies; sinds[n] holds i_n itself
         float *svals;
@@ -337,6 +339,7 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
         l.fac[q] = facs[k];
     }
     l.keys = mode == 0 ? 1u : std::min<uint32_t>(2u, X->order - 1);
+    l.flag = X->flag;
     l.facn = fused ? facs[mode] : nullptr;
     l.vals = ovr ? ovr : md.svals;
     l.perm = ovr ? md.perm : nullptr;
@@ -521,6 +524,7 @@ pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz
         X->inds[k] = nnz ? d_inds[k] : nullptr;
     }
     X->vals = d_vals;
+    X->flag = at(L.flag);
     for (uint32_t n = 0; n < order; ++n) {
         for (uint32_t k = 0; k < order; ++k) X->mode[n].sinds[k] = at(L.sinds[n][k]);
         X->mode[n].svals = reinterpret_cast<float *>(base + L.svals[n]);
@@ -616,6 +620,16 @@ pasta_status pasta_coo_create(uint32_t order, const uint64_t *dims, uint64_t nnz
     if (host_flag) return fail(PASTA_ERANGE);
     *out = X;
     return PASTA_OK;
+}
+
+pasta_status pasta_coo_check(const pasta_coo *X, void *stream)
+{
+    if (!X) return PASTA_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t host_flag = 0;
+    HIPCHK(hipMemcpyAsync(&host_flag, X->flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return host_flag ? PASTA_EINTERNAL : PASTA_OK;
 }
 
 pasta_status pasta_coo_destroy(pasta_coo *X)
@@ -1412,6 +1426,7 @@ const char *pasta_status_str(pasta_status s)
     case PASTA_EUNSUPPORTED: return "unsupported order, rank, dtype or alignment";
     case PASTA_EWORKSPACE: return "workspace too small or misaligned";
     case PASTA_EHIP: return "HIP runtime error";
+    case PASTA_EINTERNAL: return "a kernel found the preprocessed tensor inconsistent";
     }
     return "unknown status";
 }

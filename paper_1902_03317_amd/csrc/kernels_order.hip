@@ -46,6 +46,7 @@ struct MttkrpArgs {
     float *out;
     float *part;
     double *loss_part;
+    uint32_t *flag;
     uint64_t nnz;
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
     uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
@@ -597,6 +598,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                     for (int e = 0; e < VEC; ++e) contrib[e] = on ? w * q[e] : 0.0f;
                     const uint32_t rl = (uint32_t)__builtin_amdgcn_readlane((int)E.r, (m * US + u) * G + G - 1);
                     const bool moved = cur != rl;
+                    int closed = 0;
                     while (cur != rl) {  // wave-uniform: close every row that ends in this step
                         float extra[VEC];
 #pragma unroll
@@ -607,6 +609,14 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
                         // the next row: that of the first group past the current one. Only the
                         // first lane of each group votes, so the lowest set bit is that lane.
                         const uint64_t ahead = __ballot(j == 0 && ru > cur);
+                        if (ahead == 0 || ++closed > G) {
+                            // In a stream sorted by row some group is past `cur` while cur != rl,
+                            // and at most G rows end in one step. Otherwise the stream is out of
+                            // order: flag it and leave the loop (the results are then undefined).
+                            if (lane == 0 && a.flag) *a.flag = 2u;
+                            cur = rl;
+                            break;
+                        }
                         const int first_lane = __ffsll((long long)ahead) - 1;
                         cur = (uint32_t)__builtin_amdgcn_readlane((int)ru, first_lane);
                     }
@@ -905,6 +915,7 @@ hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool 
     a.nchunks = l.nchunks;
     a.row_bytes = l.ldf * (bf16 ? 2u : 4u);
     a.keys = l.keys;
+    a.flag = l.flag;
     a.alpha = l.alpha;
     return dispatch<MttkrpRun>(a, bf16, s, st, fused, l.wave);
 }

@@ -105,13 +105,14 @@ def _head_block():
     return sp, blk
 
 
-def test_autograd_finite_differences_and_dense_gradient():
+@pytest.mark.parametrize("R", [8, 32])
+def test_autograd_finite_differences_and_dense_gradient(R):
+    """R = 32 is the CP fit's rank; the entries are scaled so the model's values are O(1)."""
     from paper_1902_03317_amd.autograd import cp_loss
     sp, blk = _head_block()
     assert blk.nnz == 6000  # every cell of the block is present
-    R = 8
     rng = np.random.default_rng(9)
-    A = [rng.standard_normal((d, R)).astype(np.float32) * 0.5 for d in blk.dims]
+    A = [rng.standard_normal((d, R)).astype(np.float32) * np.float32(R ** (-1.0 / 6.0)) for d in blk.dims]
     X = upload(blk)
     masters = [t.clone().requires_grad_(True) for t in factors_dev(A)]
     loss = cp_loss(X, masters)

@@ -52,6 +52,7 @@ def check_mttkrp(coo, X, factors, tol, dtype=torch.float32, modes=None, ld=None,
         e = rel(got, want)
         errs.append(e)
         assert e <= tol, f"mode {n}: rel-Fro {e:.3e} > {tol}"
+    X.check()  # no kernel found a sorted stream out of order
     return errs
 
 

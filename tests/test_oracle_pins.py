@@ -266,6 +266,12 @@ def test_mode_orders_are_cyclic_lexicographic(oracle_lib):
             cyc = list(range(n, -1, -1)) + ([N - 1] if n < N - 1 else [])
             want = sorted(range(90), key=lambda m: tuple(int(inds[k, m]) for k in cyc) + (m,))
             assert list(orders[n]) == want
+        # the same orders as a chain of stable single-key sorts: mode N-1 by i_{N-1} out of
+        # caller order, then each mode n by i_n out of mode n-1's order
+        prev = np.argsort(inds[N - 1], kind="stable")
+        for n in range(N):
+            prev = prev[np.argsort(inds[n][prev], kind="stable")]
+            assert np.array_equal(orders[n], prev)
 
 
 def test_golden_lexicographic_order(oracle_lib):
@@ -392,3 +398,32 @@ def test_cp_als_recovers_a_planted_model(oracle_lib):
     for _ in range(60):
         U, lam, fit = oracle.cp_als_sweep(dims, inds, X.reshape(-1), U)
     assert fit > 1 - 1e-6
+
+
+def test_cp_fit_is_the_dense_relative_residual(oracle_lib):
+    """cp_fit on distinct coordinates equals 1 - ||X - [[lambda; U]]||_F / ||X||_F with the
+    model built densely (outer products) and X zero off the nonzeros."""
+    rng = np.random.default_rng(25)
+    dims = (5, 6, 4)
+    lin = rng.choice(120, 50, replace=False)
+    inds = np.stack(np.unravel_index(lin, dims)).astype(np.uint32)
+    vals = rng.standard_normal(50)
+    U = rand_factors(rng, dims, 3)
+    lam = rng.uniform(0.5, 2.0, 3)
+    X = brute.dense(dims, inds, vals)
+    model = brute.cp_full([U[0] * lam[None, :], U[1], U[2]])
+    want = 1.0 - np.linalg.norm(X - model) / np.linalg.norm(X)
+    assert abs(oracle.cp_fit(dims, inds, vals, U, lam) - want) <= 1e-12
+
+
+def test_cp_als_update_condition_number(oracle_lib):
+    """With orthonormal columns in every other factor, V = Hadamard of identities = I, so
+    the reported condition number is 1 and the update is MTTKRP scaled to unit columns."""
+    rng = np.random.default_rng(26)
+    dims = (7, 6, 5)
+    inds, vals = rand_coo(rng, dims, 40)
+    U = [np.linalg.qr(rng.standard_normal((d, 3)))[0] for d in dims]
+    Un, lam, M, kappa = oracle.cp_als_update(dims, inds, vals, U, 0)
+    assert abs(kappa - 1.0) <= 1e-12
+    assert rel(Un * lam[None, :], M) <= 1e-12
+    assert rel(M, brute.mttkrp_dense(brute.dense(dims, inds, vals), U, 0)) <= 1e-12
