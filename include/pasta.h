@@ -177,7 +177,8 @@ pasta_status pasta_cp_grad(const pasta_coo *X, const void *const *d_factors, pas
 /* One sweep of CP-ALS (alternating least squares, one of the CPD methods of
  * Section 3.1.1, whose bottleneck is the MTTKRP): for every mode n in turn,
  *   M = MTTKRP_n(X; U),  V = Hadamard_{k != n} (U_k^T U_k),
- *   U_n <- M V^{-1} (Cholesky of V),  lambda_r = ||U_n[:, r]||_2,
+ *   U_n <- M V^{-1} (V^{-1} by Gauss-Jordan elimination; V is symmetric
+ *   positive definite, so no pivoting),  lambda_r = ||U_n[:, r]||_2,
  *   U_n[:, r] /= lambda_r (zero columns stay zero).
  *   d_factors  host array of `order` device pointers to fp32 I_k x ldf
  *              factors, updated in place; rank R <= 64.

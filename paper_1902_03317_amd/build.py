@@ -47,33 +47,29 @@ def _jobs():
 
 
 def _compile(job):
-    src, obj, extra, objdir, defs = job
-    out = os.path.join(objdir, obj)
-    cmd = [HIPCC] + FLAGS + list(defs) + extra + ["-c", src, "-o", out]
+    src, obj, extra = job
+    out = os.path.join(OBJ, obj)
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {obj}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return out
 
 
-def build(jobs: int = 8, verbose: bool = False, defines=(), lib_path: str = LIB) -> str:
-    """Compile every HIP source and link libpasta.so; returns its path.
-
-    ``defines`` (e.g. ["-DPASTA_STEP=4"]) set tuning parameters; ``lib_path``
-    names the output (other paths are for side-by-side builds)."""
-    objdir = OBJ if lib_path == LIB else lib_path + ".objs"
-    os.makedirs(objdir, exist_ok=True)
+def build(jobs: int = 8, verbose: bool = False) -> str:
+    """Compile every HIP source and link libpasta.so; returns its path."""
+    os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, [j + (objdir, tuple(defines)) for j in _jobs()]))
-    tmp = lib_path + f".tmp{os.getpid()}"
+        objs = list(ex.map(_compile, _jobs()))
+    tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, lib_path)
+    os.replace(tmp, LIB)
     if verbose:
-        print(f"built {lib_path}")
-    return lib_path
+        print(f"built {LIB}")
+    return LIB
 
 
 def clean():

@@ -3,7 +3,8 @@
 // For mode n, with M = MTTKRP_n(X; U) and V = Hadamard_{k != n} (U_k^T U_k):
 //     U_n <- M V^{-1},  lambda_r = ||U_n[:, r]||_2,  U_n[:, r] /= lambda_r.
 // The R x R work is tiny; these kernels are bandwidth-bound passes over the
-// I_n x R matrices plus one small Cholesky solve in a single workgroup.
+// I_n x R matrices plus one small R x R inversion (Gauss-Jordan elimination)
+// in a single workgroup.
 // All sums run in a fixed order (deterministic).
 #include "common.h"
 

@@ -59,10 +59,7 @@ thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
     } while (0)
 
 constexpr size_t kAlign = 256;
-#ifndef PASTA_SUB
-#define PASTA_SUB 256
-#endif
-constexpr uint32_t kSub = PASTA_SUB;      // nonzeros per lane group per chunk
+constexpr uint32_t kSub = 256;           // nonzeros per lane group per chunk (run form)
 constexpr uint32_t kSampleTilesPerWave = 16;
 constexpr uint32_t kWaveChunk = 2048;    // nonzeros per chunk of the wave-run form
 constexpr uint64_t kWaveMinRowLen = 48;  // average nonzeros per row from which it is chosen

@@ -30,11 +30,7 @@ namespace {
 
 constexpr int NM1 = PASTA_NM1;
 // Nonzeros a group handles per step; their NM1 gathers are issued together.
-#ifdef PASTA_STEP
-constexpr int kStep = PASTA_STEP;
-#else
 constexpr int kStep = NM1 <= 2 ? 8 : (NM1 <= 4 ? 4 : 2);
-#endif
 
 struct MttkrpArgs {
     const uint32_t *row;
@@ -66,11 +62,7 @@ __device__ __forceinline__ T stream_load(const T *p)
 // keeps the factor rows a run touches in that XCD's own L2.
 __device__ __forceinline__ uint32_t chunk_of_wave(uint32_t nblocks)
 {
-#ifdef PASTA_NO_XCD_REMAP
-    return blockIdx.x * 4 + (threadIdx.x >> 6);
-#else
     return xcd_contiguous(blockIdx.x, nblocks) * 4 + (threadIdx.x >> 6);
-#endif
 }
 
 template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR>
@@ -85,11 +77,7 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     // Row reuse pays with bf16 factors (measured: ~8% faster per mode on the
     // 50M-nonzero Zipf tensor) but costs ~20% with fp32 rows, so it is only
     // compiled in for bf16.
-#ifdef PASTA_REUSE
-    constexpr bool kReuse = PASTA_REUSE != 0;
-#else
     constexpr bool kReuse = sizeof(FT) == 2;
-#endif
 
     const int lane = threadIdx.x & 63;
     const uint32_t chunk = chunk_of_wave(gridDim.x);
