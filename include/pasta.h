@@ -137,6 +137,23 @@ pasta_status pasta_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *
                           uint32_t rank, uint32_t ldf, const float *d_vals_override, float alpha, float *d_out,
                           uint32_t ldo, void *d_work, size_t work_bytes, void *stream);
 
+/* pasta_mttkrp for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments and the same kernels and results, without d_work. Its scratch (the
+ * partial rows of the chunks a row spans) is a fixed array of
+ * PASTA_STATIC_SCRATCH_BYTES inside the library; each GPU it runs on holds its own
+ * copy until the process ends. It allocates nothing (no hipMalloc, no library
+ * allocation). Returns PASTA_EWORKSPACE, and launches nothing, if the call needs
+ * more scratch than the array holds (pasta_mttkrp_workspace_bytes gives an upper
+ * bound of the need: e.g. R = 64 fp32 at up to ~130M nonzeros fits). All calls on
+ * one GPU share its array and it keeps the last call's contents (no call relies on
+ * them: every slot a call reads, the same call wrote first), so calls that overlap
+ * in time on one GPU race: serialise them (one stream, or events). */
+#define PASTA_STATIC_SCRATCH_BYTES (64u << 20)
+pasta_status pasta_mttkrp_static(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                                 uint32_t rank, uint32_t ldf, const float *d_vals_override, float alpha, float *d_out,
+                                 uint32_t ldo, void *stream);
+
 /* The same product computed the way the suite's parallel CPU code does with
  * atomics (Section 5.3): nonzeros in caller order, one atomic row update
  * per nonzero, no sorting. Kept as a reference point for measurements;

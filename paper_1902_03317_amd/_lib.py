@@ -42,6 +42,7 @@ SIGNATURES = {
     "pasta_mttkrp_workspace_bytes": [P, U32, U32, ctypes.c_int, ctypes.POINTER(SZ)],
     "pasta_mttkrp": [P, U32, P, ctypes.c_int, U32, U32, P, F32, P, U32, P, SZ, P],
     "pasta_mttkrp_atomic": [P, U32, P, ctypes.c_int, U32, U32, P, U32, P],
+    "pasta_mttkrp_static": [P, U32, P, ctypes.c_int, U32, U32, P, F32, P, U32, P],
     "pasta_cp_sample": [P, P, ctypes.c_int, U32, U32, P, P],
     "pasta_cp_workspace_bytes": [P, U32, ctypes.c_int, ctypes.POINTER(SZ)],
     "pasta_cp_residual_loss": [P, P, ctypes.c_int, U32, U32, P, P, P, SZ, P],

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "../../include/pasta.h"
@@ -678,6 +679,67 @@ pasta_status pasta_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *
     if (s != PASTA_OK) return s;
     return run_mttkrp(X, mode, d_factors, dtype, rank, ldf, d_vals_override, alpha, d_out, ldo, d_work, work_bytes,
                       false, nullptr, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// Scratch of pasta_mttkrp_static: a fixed array in the library's code object, so
+// that entry point allocates nothing. Every GPU the library runs on holds its own
+// copy (PASTA_STATIC_SCRATCH_BYTES) until the process ends. In host code the name
+// `scratch` is only a handle for hipGetSymbolAddress; the device address of each
+// GPU's copy is looked up once per device and kept in g_scratch_addr.
+static __device__ __align__(256) unsigned char scratch[PASTA_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+
+// The device address of `scratch` on the device that runs `st` (looked up with that
+// device current the first time, then cached).
+pasta_status static_scratch(hipStream_t st, void **addr)
+{
+    int dev = -1, cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (st)
+        HIPCHK(hipStreamGetDevice(st, &dev));
+    else
+        dev = cur;
+    if (dev < 0 || dev >= kMaxDevices) return PASTA_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        if (dev != cur) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) HIPCHK(hipSetDevice(cur));
+        HIPCHK(e);
+        if (!p) return PASTA_EHIP;
+        g_scratch_addr[dev] = p;
+    }
+    *addr = g_scratch_addr[dev];
+    return PASTA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pasta_status pasta_mttkrp_static(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
+                                 uint32_t rank, uint32_t ldf, const float *d_vals_override, float alpha, float *d_out,
+                                 uint32_t ldo, void *stream)
+{
+    if (!X || mode >= X->order || rank == 0 || ldf < rank || ldo < rank || !d_out) return PASTA_EINVAL;
+    if (dtype != PASTA_F32 && dtype != PASTA_BF16) return PASTA_EUNSUPPORTED;
+    if (rank > 256) return PASTA_EUNSUPPORTED;
+    pasta_status s = check_factors(X, d_factors, mode);
+    if (s != PASTA_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *work = nullptr;
+    s = static_scratch(st, &work);
+    if (s != PASTA_OK) return s;
+    // the same kernels as pasta_mttkrp, their scratch in the static array; a call that
+    // needs more than it holds returns PASTA_EWORKSPACE before anything is launched
+    return run_mttkrp(X, mode, d_factors, dtype, rank, ldf, d_vals_override, alpha, d_out, ldo, work,
+                      PASTA_STATIC_SCRATCH_BYTES, false, nullptr, st);
 }
 
 pasta_status pasta_mttkrp_atomic(const pasta_coo *X, uint32_t mode, const void *const *d_factors, pasta_dtype dtype,
