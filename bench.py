@@ -320,8 +320,8 @@ def gather_ceiling(ctx: Ctx, L: int) -> dict:
         table = torch.randint(0, 1 << 30, (nbytes // 4,), dtype=torch.int32, device=ctx.dev)
         for share_name, share in (("distinct", 1), ("wave_shared", 64 // L)):
             def run():
-                st = ctx.plib.pasta_probe_gather(table.data_ptr(), rows, L, share, steps, blocks, out.data_ptr(),
-                                                 ctx.s_ptr)
+                st = ctx.plib.pasta_probe_gather(table.data_ptr(), rows, L, share, 64 // L, steps, blocks,
+                                                 out.data_ptr(), ctx.s_ptr)
                 assert st == 0, st
             t = ctx.timed(run, 5)
             res[f"{name}_{share_name}_gbps"] = round(blocks * 256 * steps * 16 / (t * 1e-3) / 1e9, 1)

@@ -244,10 +244,13 @@ pasta_status pasta_last_mttkrp_form(int *form);
  * ceiling the MTTKRP kernels' factor-row gathers are compared with. Launches
  * `blocks` workgroups of 4 waves; each wave is 64 / lanes groups of `lanes`
  * lanes, and in each of `steps` steps every group reads one row of
- * lanes x 16 bytes from d_table (lane j reads bytes 16j .. 16j+15), the row
- * drawn by a hash of (wave, step, group / share): share = 1 gives every group
- * its own row, share = 64 / lanes one row per wave. Eight steps' loads are in
- * flight at a time. Bytes delivered = blocks * 256 * steps * 16.
+ * lanes x 16 bytes from d_table (lane j reads bytes 16j .. 16j+15), the rows
+ * starting at a hash of (wave, group / share) and advancing by an odd stride per
+ * step: share = 1 gives every group its own row, share = 64 / lanes one row per
+ * wave. Only groups 0 .. active-1
+ * load (1 <= active <= 64 / lanes; the others' lanes are masked off). Eight
+ * steps' loads are in flight at a time. Bytes delivered =
+ * blocks * 256 * steps * 16 * active / (64 / lanes).
  *   d_table  rows * lanes * 16 bytes, 16-byte aligned; rows a power of two
  *            (the table's size picks the cache level that serves it).
  *   lanes    4, 8 or 16 (the group widths of the MTTKRP kernels' 16-byte
@@ -256,8 +259,8 @@ pasta_status pasta_last_mttkrp_form(int *form);
  *   d_out    blocks * 256 * 16 bytes, 16-byte aligned; receives a fold of
  *            the loaded words (kept so that no load is dropped).
  * Asynchronous on `stream`. */
-pasta_status pasta_probe_gather(const void *d_table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t steps,
-                                uint32_t blocks, void *d_out, void *stream);
+pasta_status pasta_probe_gather(const void *d_table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t active,
+                                uint32_t steps, uint32_t blocks, void *d_out, void *stream);
 
 /* d_x[i] *= (float)*d_alpha for i < count: scales a gradient by an upstream
  * derivative held on the device (no host round trip). */

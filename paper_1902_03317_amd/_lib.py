@@ -50,7 +50,7 @@ SIGNATURES = {
     "pasta_cp_grad": [P, P, ctypes.c_int, U32, U32, F32, P, U32, P, P, SZ, P],
     "pasta_cast_f32_to_bf16": [P, P, U64, P],
     "pasta_scale_f32": [P, U64, P, P],
-    "pasta_probe_gather": [P, U32, U32, U32, U32, U32, P, P],
+    "pasta_probe_gather": [P, U32, U32, U32, U32, U32, U32, P, P],
     "pasta_arm_kernel_events": [P, P],
     "pasta_set_mttkrp_form": [ctypes.c_int],
     "pasta_last_mttkrp_form": [P],

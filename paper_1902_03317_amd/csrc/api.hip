@@ -1017,15 +1017,17 @@ pasta_status pasta_arm_kernel_events(void *ev_start, void *ev_stop)
     return PASTA_OK;
 }
 
-pasta_status pasta_probe_gather(const void *d_table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t steps,
-                                uint32_t blocks, void *d_out, void *stream)
+pasta_status pasta_probe_gather(const void *d_table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t active,
+                                uint32_t steps, uint32_t blocks, void *d_out, void *stream)
 {
     if (!d_table || !d_out || rows == 0 || (rows & (rows - 1)) != 0 || blocks == 0) return PASTA_EINVAL;
     if (lanes != 4 && lanes != 8 && lanes != 16) return PASTA_EUNSUPPORTED;
     const uint32_t G = 64u / lanes;
     if (share == 0 || share > G || (share & (share - 1)) != 0 || steps == 0 || steps % 8 != 0) return PASTA_EINVAL;
+    if (active == 0 || active > G) return PASTA_EINVAL;
     if (((uintptr_t)d_table % 16) != 0 || ((uintptr_t)d_out % 16) != 0) return PASTA_EUNSUPPORTED;
-    HIPCHK(launch_gather_probe(d_table, rows, lanes, share, steps, blocks, d_out, static_cast<hipStream_t>(stream)));
+    HIPCHK(launch_gather_probe(d_table, rows, lanes, share, active, steps, blocks, d_out,
+                               static_cast<hipStream_t>(stream)));
     return PASTA_OK;
 }
 

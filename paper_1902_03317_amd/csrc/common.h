@@ -277,8 +277,8 @@ hipError_t launch_sumsq(const float *x, uint64_t n, double *partial, uint32_t np
 
 // Measurement (calibrate.hip): `blocks` workgroups of row gathers, L x 16 bytes
 // per row, rows hashed over a power-of-two table; see pasta_probe_gather.
-hipError_t launch_gather_probe(const void *table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t steps,
-                               uint32_t blocks, void *out, hipStream_t st);
+hipError_t launch_gather_probe(const void *table, uint32_t rows, uint32_t lanes, uint32_t share, uint32_t active,
+                               uint32_t steps, uint32_t blocks, void *out, hipStream_t st);
 
 // Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
 // b % 8). This renumbering gives each XCD one contiguous run of logical
