@@ -64,6 +64,9 @@ constexpr uint32_t kSub = 256;           // nonzeros per lane group per chunk (r
 constexpr uint32_t kSampleTilesPerWave = 16;
 constexpr uint32_t kWaveChunk = 2048;    // nonzeros per chunk of the wave-run form
 constexpr uint64_t kWaveMinRowLen = 48;  // average nonzeros per row from which it is chosen
+// LDS a factor may take in the wave-run form: three workgroups of it fit a CU's 160 KiB
+// (the occupancy its registers allow at R = 32..64)
+constexpr uint64_t kLdsFactorBytes = 52u << 10;
 int g_mttkrp_form = 0;                   // 0 automatic, 1 run form, 2 wave-run form
 int g_last_form = 0;                     // form of the most recent MTTKRP main-kernel launch
 
@@ -331,12 +334,33 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
     // kernel reuses their rows along runs). Mode n's order is lexicographic in
     // (i_n, i_{n-1}, ..., i_0) and then i_{N-1}: mode 0's has one key after i_0 (then
     // caller position), every other mode's at least two.
+    uint32_t qmode[kMaxOrder];
     for (uint32_t q = 0; q + 1 < X->order; ++q) {
         const uint32_t k = (mode + X->order - 1 - q) % X->order;
         l.idx[q] = md.sinds[k];
         l.fac[q] = facs[k];
+        qmode[q] = k;
     }
     l.keys = mode == 0 ? 1u : std::min<uint32_t>(2u, X->order - 1);
+    // Wave-run form, orders 3-5: the smallest factor after the second key whose rows fit
+    // kLdsFactorBytes moves to the last place and is read from LDS (the kernel stages it
+    // per workgroup).
+    l.lds_rows = 0;
+    if (wave && !ovr && !s.strided && (s.lanes == 8 || s.lanes == 16) && X->order >= 3 && X->order <= 5) {
+        const uint32_t last = X->order - 2;
+        uint32_t best = 0;
+        for (uint32_t q = 1; q <= last; ++q) {
+            const uint64_t bytes = X->dims[qmode[q]] * (uint64_t)s.lanes * 16u;
+            if (bytes <= kLdsFactorBytes && (best == 0 || X->dims[qmode[q]] < X->dims[qmode[best]])) best = q;
+        }
+        if (best) {
+            std::swap(l.idx[best], l.idx[last]);
+            std::swap(l.fac[best], l.fac[last]);
+            std::swap(qmode[best], qmode[last]);
+            if (best == 1 || last == 1) l.keys = 1;  // factor 1 is no longer the third key
+            l.lds_rows = (uint32_t)X->dims[qmode[last]];
+        }
+    }
     l.flag = X->flag;
     l.facn = fused ? facs[mode] : nullptr;
     l.vals = ovr ? ovr : md.svals;

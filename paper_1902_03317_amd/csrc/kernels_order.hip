@@ -47,6 +47,7 @@ struct MttkrpArgs {
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
     uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
     uint32_t keys;       // factors 0 .. keys-1 are the stream's sort keys after i_n, in key order
+    uint32_t lds_rows;   // wave-run form: rows of factor NM1-1, which is read from LDS (0: none)
     float alpha;
 };
 
@@ -359,7 +360,10 @@ constexpr int fused_group_steps(bool bf16)
 // tiles ahead are loaded behind them. Rows crossing the chunk's edges leave
 // partials in the same slots as the run form, for the same fixup.
 // ---------------------------------------------------------------------------
-template <typename FT, int VEC, int L, bool FUSED, bool OVR>
+// With LDSF the last factor is small enough for LDS: each workgroup copies its
+// rows there once (row stride L x 16 bytes, the slices the lanes read), and its
+// gathers become LDS reads, which leave the vector memory pipeline to the others.
+template <typename FT, int VEC, int L, bool FUSED, bool OVR, bool LDSF>
 __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;                 // nonzeros per step
@@ -370,6 +374,16 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     using S = Slice<FT, VEC, false>;
     using Packed = typename S::Packed;
     const int lane = threadIdx.x & 63;
+    extern __shared__ uint4 lds_fac[];
+    if constexpr (LDSF) {  // every wave of the workgroup takes part, before any leaves
+        const uint32_t slices = (a.rank * (uint32_t)sizeof(FT) + 15u) / 16u;  // active 16-byte slices per row
+        const char *src = static_cast<const char *>(a.fac[NM1 - 1]);
+        for (uint32_t e = threadIdx.x; e < a.lds_rows * (uint32_t)L; e += 256u) {
+            const uint32_t r = e / (uint32_t)L, sl = e % (uint32_t)L;
+            if (sl < slices) lds_fac[e] = *reinterpret_cast<const uint4 *>(src + (uint64_t)r * a.row_bytes + sl * 16u);
+        }
+        __syncthreads();
+    }
     const uint32_t chunk = chunk_of_wave(gridDim.x);
     if (chunk >= a.nchunks) return;  // whole wave leaves together
     const int g = lane / L, j = lane % L;
@@ -429,8 +443,13 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
         }
     };
     auto gather = [&](int k, uint32_t iu, Packed &pk) __attribute__((always_inline)) {
-        const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)(lane_on ? j : 0) * 16u;
-        const uint4 t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+        uint4 t;
+        if (LDSF && k == NM1 - 1) {
+            t = lds_fac[iu * (uint32_t)L + (uint32_t)(lane_on ? j : 0)];
+        } else {
+            const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)(lane_on ? j : 0) * 16u;
+            t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+        }
         pk.w[0] = t.x;
         pk.w[1] = t.y;
         pk.w[2] = t.z;
@@ -796,12 +815,22 @@ hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, bool wave, hipStream_t
     const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
     if constexpr (!STRIDED) {
         if (wave) {
+            if constexpr ((L == 8 || L == 16) && NM1 >= 2 && NM1 <= 4) {
+                if (args.lds_rows && !args.perm) {  // the host sized lds_rows to fit (kLdsFactorBytes)
+                    const size_t lds = (size_t)args.lds_rows * L * 16;
+                    if (fused)
+                        mttkrp_wave_kernel<FT, VEC, L, true, false, true><<<grid, 256, lds, st>>>(args);
+                    else
+                        mttkrp_wave_kernel<FT, VEC, L, false, false, true><<<grid, 256, lds, st>>>(args);
+                    return hipGetLastError();
+                }
+            }
             if (fused)
-                mttkrp_wave_kernel<FT, VEC, L, true, false><<<grid, 256, 0, st>>>(args);
+                mttkrp_wave_kernel<FT, VEC, L, true, false, false><<<grid, 256, 0, st>>>(args);
             else if (args.perm)
-                mttkrp_wave_kernel<FT, VEC, L, false, true><<<grid, 256, 0, st>>>(args);
+                mttkrp_wave_kernel<FT, VEC, L, false, true, false><<<grid, 256, 0, st>>>(args);
             else
-                mttkrp_wave_kernel<FT, VEC, L, false, false><<<grid, 256, 0, st>>>(args);
+                mttkrp_wave_kernel<FT, VEC, L, false, false, false><<<grid, 256, 0, st>>>(args);
             return hipGetLastError();
         }
     }
@@ -903,6 +932,7 @@ hipError_t PASTA_CAT(launch_mttkrp_nm1_, PASTA_NM1)(const MttkrpLaunch &l, bool 
     a.nchunks = l.nchunks;
     a.row_bytes = l.ldf * (bf16 ? 2u : 4u);
     a.keys = l.keys;
+    a.lds_rows = l.lds_rows;
     a.flag = l.flag;
     a.alpha = l.alpha;
     return dispatch<MttkrpRun>(a, bf16, s, st, fused, l.wave);
