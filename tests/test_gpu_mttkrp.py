@@ -92,6 +92,26 @@ def test_zipf_order4_and_order5():
         check_mttkrp(coo, X, f, TOL_BF16, dtype=torch.bfloat16)
 
 
+@pytest.mark.parametrize("cfg,dims,R", [(3, (30_000, 3000, 208, 209), 64), (3, (30_000, 3000, 416, 417), 32),
+                                         (2, (5000, 416, 417), 32), (5, (20_000, 2000, 1000, 208, 100), 64)])
+def test_lds_factor_at_its_size_limit(cfg, dims, R):
+    """The wave-run form (orders 3-5) reads the smallest factor after the second key from LDS
+    when its rows fit 52 KiB: 208 rows of 256 bytes (fp32, R = 64) or 416 of 128 bytes (fp32
+    R = 32, bf16 R = 64); one row more takes the global path. The factor that qualifies
+    differs by mode; fp32 and bf16 factors, every mode, against the oracle."""
+    sp = synth.CONFIGS[cfg].scaled(400_000, dims=dims)
+    coo = synth.make_coo(sp)
+    X = upload(coo)
+    f = synth.make_factors(sp, rank=R)
+    check_mttkrp(coo, X, f, TOL_F32)
+    check_mttkrp(coo, X, f, TOL_BF16, dtype=torch.bfloat16)
+    fd = factors_dev(f, torch.bfloat16)
+    fo = oracle_factors(f, bf16=True)
+    for n in range(coo.order):  # accumulation only: the fp32 bar against the bf16-rounded factors
+        got = api().mttkrp(X, fd, n).cpu().numpy().astype(np.float64)
+        assert rel(got, oracle.mttkrp(coo.dims, coo.inds, coo.vals, fo, n, "priv")) <= TOL_F32
+
+
 @pytest.mark.parametrize("R", [1, 3, 8, 24, 48, 100, 256])
 def test_rank_generality(R):
     sp, coo = small_zipf(nnz=50_000, dims=(700, 500, 300))
