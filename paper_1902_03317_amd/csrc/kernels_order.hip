@@ -368,7 +368,11 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;                 // nonzeros per step
     // steps whose gathers go out together, and such groups per tile of 64 entries
-    constexpr int US_MAX = FUSED ? fused_group_steps(sizeof(FT) == 2) : kStep;
+    // With a factor in LDS, a step has one memory gather fewer; with fp32 rows the LDS form
+    // then keeps 8 steps of the others in flight (measured at order 5: modes 1-3 6.3-6.7 ->
+    // 5.9-6.1 ms, although the registers allow one wave per SIMD fewer; with bf16 rows, in
+    // the other forms and in the fused kernel more steps were slower).
+    constexpr int US_MAX = FUSED ? fused_group_steps(sizeof(FT) == 2) : (LDSF && sizeof(FT) == 4 ? 8 : kStep);
     constexpr int US = L < US_MAX ? L : US_MAX;
     constexpr int MS = L / US;
     using S = Slice<FT, VEC, false>;
