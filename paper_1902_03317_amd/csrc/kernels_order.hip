@@ -46,7 +46,7 @@ struct MttkrpArgs {
     uint64_t nnz;
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
     uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
-    uint32_t keys;       // factors 0 .. keys-1 are the stream's sort keys after i_n, in key order
+    uint32_t keys;       // factors 0 .. keys-1 are the stream's sort keys after i_n, in key order (0..2)
     uint32_t lds_rows;   // wave-run form: rows of factor NM1-1, which is read from LDS (0: none)
     float alpha;
 };
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
             const uint32_t mlast = (uint32_t)__builtin_amdgcn_readlane((int)E.r, llast);
             const uint32_t k0f = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], lfirst);
             const uint32_t k0l = (uint32_t)__builtin_amdgcn_readlane((int)E.i[0], llast);
-            if (mlast == cur && k0f == k0l) {  // one factor-0 row for the whole group of steps
+            if (a.keys >= 1 && mlast == cur && k0f == k0l) {  // one factor-0 row for the whole group of steps
                 bool one = false;
                 if constexpr (NM1 >= 3) {
                     one = a.keys >= 2 && __builtin_amdgcn_readlane((int)E.i[1], lfirst) ==
