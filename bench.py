@@ -340,18 +340,19 @@ def copy_rate(ctx: Ctx) -> float:
     return 2 * a.numel() * 4 / (t * 1e-3) / 1e9
 
 
-def measured_traffic(w: Workload, kernel, dtype: str):
-    """rocprofv3 fabric bytes per launch of the main kernel, if committed for these sources."""
+def measured_counters(w: Workload, kernel, dtype: str) -> dict:
+    """rocprofv3 counters of the main kernel committed for these sources: fabric bytes per
+    launch and vector memory read instructions per launch (empty if none match)."""
     if not isinstance(kernel, str):
-        return None
+        return {}
     p = traffic_file(kernel, w.spec.name, w.R, dtype)
     if not os.path.exists(p):
-        return None
+        return {}
     tr = json.load(open(p))
     if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == w.spec.name and \
             kernel in tr.get("kernel", "") and tr.get("factor_dtype") == dtype:
-        return tr.get("bytes_per_launch")
-    return None
+        return tr
+    return {}
 
 
 def kernel_label(forms):
@@ -643,7 +644,9 @@ def main():
     sf = 2 if head == "bf16" else 4
     qmin = [bytes_compulsory(w.coo.dims, R, sf, M, n) for n in range(N)]
     achieved = sum(qmin) / (sum(kern[head]) * 1e-3) / 1e9
-    traffic = measured_traffic(w, kernel, head)
+    counters = measured_counters(w, kernel, head)
+    traffic = counters.get("bytes_per_launch")
+    vmem = counters.get("vmem_rd_instr_per_launch")
     mean_launch = sum(kern[head]) / N * 1e-3
     log("gather-pipeline probe and device copy")
     ceil = gather_ceiling(ctx, lanes_per_row(R, sf))
@@ -674,6 +677,11 @@ def main():
                      "copy_gbps": round(copy_gbps, 1)},
         "gather_pipeline": {"nominal_gbps": round(grate, 1), **ceil,
                             "nominal_frac_of_l2_distinct": round(grate / ceil["l2_distinct_gbps"], 4),
+                            # the kernel's load instructions (rocprofv3 SQ_INSTS_VMEM_RD per launch) per ns,
+                            # against the probe's rate for L2-resident distinct rows
+                            "kernel_vmem_instr_per_ns": round(vmem / (mean_launch * 1e9), 2) if vmem else None,
+                            "instr_frac_of_l2_distinct": round(vmem / (mean_launch * 1e9) /
+                                                               ceil["l2_distinct_instr_per_ns"], 4) if vmem else None,
                             "note": "the factor-row bytes the method reads per second (every row of every nonzero "
                                     "counted, also rows the kernel holds in registers or reads from LDS) vs the "
                                     "probe's rate for the same 16-byte-per-lane row gathers"},
