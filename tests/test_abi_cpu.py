@@ -45,6 +45,15 @@ def test_status_strings_and_host_argument_checks():
     assert lib.pasta_coo_workspace_bytes(3, None, 10, ctypes.byref(n)) == 1
     zero = (ctypes.c_uint64 * 3)(100, 0, 60)
     assert lib.pasta_coo_workspace_bytes(3, zero, 10, ctypes.byref(n)) == 1
+    # the largest sizes taken: nnz < 2^32 (32-bit positions), order 8
+    assert lib.pasta_coo_workspace_bytes(3, dims, (1 << 32) - 1, ctypes.byref(n)) == 0
+    assert lib.pasta_coo_workspace_bytes(3, dims, 1 << 32, ctypes.byref(n)) == 3
+    dims8 = (ctypes.c_uint64 * 8)(*([4] * 8))
+    assert lib.pasta_coo_workspace_bytes(8, dims8, 1000, ctypes.byref(n)) == 0
+    # the static-scratch entry point and the check refuse a null handle before touching the device
+    assert lib.pasta_mttkrp_static(None, 0, None, 0, 8, 8, None, 1.0, None, 8, None) == 1
+    assert lib.pasta_coo_check(None, None) == 1
+    assert lib.pasta_status_str(6) == b"a kernel found the preprocessed tensor inconsistent"
     h = ctypes.c_void_p()
     # a workspace that is too small is refused before anything touches the device
     assert lib.pasta_coo_create(3, dims, 0, None, None, None, 0, None, ctypes.byref(h)) == 4

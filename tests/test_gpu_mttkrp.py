@@ -92,6 +92,31 @@ def test_zipf_order4_and_order5():
         check_mttkrp(coo, X, f, TOL_BF16, dtype=torch.bfloat16)
 
 
+@pytest.mark.parametrize("dims", [(3000, 2000), (40, 30, 20, 10, 8, 6), (20, 16, 12, 10, 8, 6, 5),
+                                  (12, 10, 8, 7, 6, 5, 4, 3)])
+def test_orders_2_and_6_to_8(dims):
+    """The smallest order and the largest ones the library takes (2 <= N <= 8), each with
+    its own compiled kernels: uniform distinct coordinates (long rows for the small modes,
+    so the wave-run form also runs), fp32 and bf16 factors, every mode, and the fused CP
+    gradient, against the oracle."""
+    from paper_1902_03317_amd.synth import TensorSpec
+    N = len(dims)
+    cells = int(np.prod(dims))
+    sp = TensorSpec(f"uniform-order{N}", dims, min(300_000, cells // 3), 32, (None,) * N, "uniform", True,
+                    synth.BASE_SEED + 100 + N)
+    coo = synth.make_coo(sp)
+    X = upload(coo)
+    check_preprocess(coo, X)
+    f = synth.make_factors(sp, scale=synth.cp_planted_scale(32, N))
+    check_mttkrp(coo, X, f, TOL_F32)
+    check_mttkrp(coo, X, f, TOL_BF16, dtype=torch.bfloat16)
+    loss, grads = api().cp_grad(X, factors_dev(f))
+    wl, wg = oracle.cp_grad(coo.dims, coo.inds, coo.vals, oracle_factors(f), "priv")
+    assert abs(loss.item() - wl) <= 1e-5 * wl
+    for n in range(N):
+        assert rel(grads[n].cpu().numpy(), wg[n]) <= TOL_F32, n
+
+
 @pytest.mark.parametrize("cfg,dims,R", [(3, (30_000, 3000, 208, 209), 64), (3, (30_000, 3000, 416, 417), 32),
                                          (2, (5000, 416, 417), 32), (5, (20_000, 2000, 1000, 208, 100), 64)])
 def test_lds_factor_at_its_size_limit(cfg, dims, R):
