@@ -342,12 +342,13 @@ pasta_status run_mttkrp(const pasta_coo *X, uint32_t mode, const void *const *fa
         qmode[q] = k;
     }
     l.keys = mode == 0 ? 1u : std::min<uint32_t>(2u, X->order - 1);
-    // Wave-run form, orders 3-5: the smallest factor after the second key whose rows fit
-    // kLdsFactorBytes moves to the last place and is read from LDS (the kernel stages it
-    // per workgroup). The second key's factor stays first even when it is small: its
-    // reuse along runs did as well as LDS would (measured on the order-4 and -5 tensors).
+    // Orders 3-5, both kernel forms: the smallest factor after the second key whose rows
+    // fit kLdsFactorBytes moves to the last place and is read from LDS (the kernel stages
+    // it per workgroup). The second key's factor stays first even when it is small: its
+    // reuse along runs in the wave-run form did as well as LDS would (measured on the
+    // order-4 and -5 tensors).
     l.lds_rows = 0;
-    if (wave && !ovr && !s.strided && (s.lanes == 8 || s.lanes == 16) && X->order >= 3 && X->order <= 5) {
+    if (!ovr && !s.strided && (s.lanes == 8 || s.lanes == 16) && X->order >= 3 && X->order <= 5) {
         const uint32_t last = X->order - 2;
         uint32_t best = 0;
         for (uint32_t q = 1; q <= last; ++q) {

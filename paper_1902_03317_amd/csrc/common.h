@@ -178,7 +178,7 @@ struct MttkrpLaunch {
     uint32_t sub;                    // nonzeros per group per chunk (wave form: per chunk)
     uint32_t nchunks;
     uint32_t keys;                   // leading factors whose indices are sort keys of the stream
-    uint32_t lds_rows;               // wave-run form: rows of the last factor, read from LDS (0: none)
+    uint32_t lds_rows;               // rows of the last factor, read from LDS (0: none)
     uint32_t *flag;                  // set to 2 if the stream is found out of order (nullable)
     float alpha;
     bool wave;                       // the wave-run form (contiguous shapes)

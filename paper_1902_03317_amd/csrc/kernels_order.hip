@@ -47,7 +47,7 @@ struct MttkrpArgs {
     uint32_t ldf, ldo, ldp, rank, sub, nchunks;
     uint32_t row_bytes;  // ldf * element size (contiguous shapes: 32-bit row offsets)
     uint32_t keys;       // factors 0 .. keys-1 are the stream's sort keys after i_n, in key order (0..2)
-    uint32_t lds_rows;   // wave-run form: rows of factor NM1-1, which is read from LDS (0: none)
+    uint32_t lds_rows;   // rows of factor NM1-1, which is read from LDS (0: none)
     float alpha;
 };
 
@@ -66,7 +66,25 @@ __device__ __forceinline__ uint32_t chunk_of_wave(uint32_t nblocks)
     return xcd_contiguous(blockIdx.x, nblocks) * 4 + (threadIdx.x >> 6);
 }
 
-template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR>
+// A factor small enough for LDS (the host sizes it; the last of the list): every
+// workgroup copies its rows there once, with a row stride of L x 16 bytes (the
+// slices the lanes read), so its gathers become LDS reads and leave the vector
+// memory pipeline to the other factors. Every wave of the workgroup takes part,
+// before any of them leaves.
+template <typename FT, int L>
+__device__ __forceinline__ void stage_lds_factor(const MttkrpArgs &a, uint4 *lds)
+{
+    const uint32_t slices = (a.rank * (uint32_t)sizeof(FT) + 15u) / 16u;  // active 16-byte slices per row
+    const char *src = static_cast<const char *>(a.fac[NM1 - 1]);
+    for (uint32_t e = threadIdx.x; e < a.lds_rows * (uint32_t)L; e += 256u) {
+        const uint32_t r = e / (uint32_t)L, sl = e % (uint32_t)L;
+        if (sl < slices) lds[e] = *reinterpret_cast<const uint4 *>(src + (uint64_t)r * a.row_bytes + sl * 16u);
+    }
+    __syncthreads();
+}
+
+// With LDSF (contiguous shapes) the last factor is read from LDS.
+template <typename FT, int VEC, int L, bool STRIDED, bool FUSED, bool OVR, bool LDSF>
 __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
 {
     constexpr int G = kWave / L;
@@ -80,7 +98,10 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
     // compiled in for bf16.
     constexpr bool kReuse = sizeof(FT) == 2;
 
+    static_assert(!(LDSF && STRIDED), "LDS rows have the contiguous slice layout");
     const int lane = threadIdx.x & 63;
+    extern __shared__ uint4 lds_fac[];
+    if constexpr (LDSF) stage_lds_factor<FT, L>(a, lds_fac);
     const uint32_t chunk = chunk_of_wave(gridDim.x);
     if (chunk >= a.nchunks) return;  // whole wave leaves together
     const int g = lane / L, j = lane % L;
@@ -156,8 +177,13 @@ __global__ __launch_bounds__(256) void mttkrp_seg_kernel(const MttkrpArgs a)
         if constexpr (STRIDED) {
             S::load(static_cast<const FT *>(a.fac[k]) + (uint64_t)iu * a.ldf, jj, a.rank, pk);
         } else {
-            const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)jj * 16u;
-            const uint4 t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+            uint4 t;
+            if (LDSF && k == NM1 - 1) {
+                t = lds_fac[iu * (uint32_t)L + (uint32_t)jj];
+            } else {
+                const uint32_t off = __umul24(iu, a.row_bytes) + (uint32_t)jj * 16u;
+                t = *reinterpret_cast<const uint4 *>(static_cast<const char *>(a.fac[k]) + off);
+            }
             pk.w[0] = t.x;
             pk.w[1] = t.y;
             pk.w[2] = t.z;
@@ -360,9 +386,7 @@ constexpr int fused_group_steps(bool bf16)
 // tiles ahead are loaded behind them. Rows crossing the chunk's edges leave
 // partials in the same slots as the run form, for the same fixup.
 // ---------------------------------------------------------------------------
-// With LDSF the last factor is small enough for LDS: each workgroup copies its
-// rows there once (row stride L x 16 bytes, the slices the lanes read), and its
-// gathers become LDS reads, which leave the vector memory pipeline to the others.
+// With LDSF the last factor is read from LDS.
 template <typename FT, int VEC, int L, bool FUSED, bool OVR, bool LDSF>
 __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
 {
@@ -379,15 +403,7 @@ __global__ __launch_bounds__(256) void mttkrp_wave_kernel(const MttkrpArgs a)
     using Packed = typename S::Packed;
     const int lane = threadIdx.x & 63;
     extern __shared__ uint4 lds_fac[];
-    if constexpr (LDSF) {  // every wave of the workgroup takes part, before any leaves
-        const uint32_t slices = (a.rank * (uint32_t)sizeof(FT) + 15u) / 16u;  // active 16-byte slices per row
-        const char *src = static_cast<const char *>(a.fac[NM1 - 1]);
-        for (uint32_t e = threadIdx.x; e < a.lds_rows * (uint32_t)L; e += 256u) {
-            const uint32_t r = e / (uint32_t)L, sl = e % (uint32_t)L;
-            if (sl < slices) lds_fac[e] = *reinterpret_cast<const uint4 *>(src + (uint64_t)r * a.row_bytes + sl * 16u);
-        }
-        __syncthreads();
-    }
+    if constexpr (LDSF) stage_lds_factor<FT, L>(a, lds_fac);
     const uint32_t chunk = chunk_of_wave(gridDim.x);
     if (chunk >= a.nchunks) return;  // whole wave leaves together
     const int g = lane / L, j = lane % L;
@@ -817,18 +833,25 @@ template <typename FT, int VEC, int L, bool STRIDED>
 hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, bool wave, hipStream_t st)
 {
     const unsigned grid = (unsigned)((args.nchunks + 3) / 4);
+    if constexpr (!STRIDED && (L == 8 || L == 16) && NM1 >= 2 && NM1 <= 4) {
+        if (args.lds_rows && !args.perm) {  // the host sized lds_rows to fit (kLdsFactorBytes)
+            const size_t lds = (size_t)args.lds_rows * L * 16;
+            if (wave) {
+                if (fused)
+                    mttkrp_wave_kernel<FT, VEC, L, true, false, true><<<grid, 256, lds, st>>>(args);
+                else
+                    mttkrp_wave_kernel<FT, VEC, L, false, false, true><<<grid, 256, lds, st>>>(args);
+            } else {
+                if (fused)
+                    mttkrp_seg_kernel<FT, VEC, L, false, true, false, true><<<grid, 256, lds, st>>>(args);
+                else
+                    mttkrp_seg_kernel<FT, VEC, L, false, false, false, true><<<grid, 256, lds, st>>>(args);
+            }
+            return hipGetLastError();
+        }
+    }
     if constexpr (!STRIDED) {
         if (wave) {
-            if constexpr ((L == 8 || L == 16) && NM1 >= 2 && NM1 <= 4) {
-                if (args.lds_rows && !args.perm) {  // the host sized lds_rows to fit (kLdsFactorBytes)
-                    const size_t lds = (size_t)args.lds_rows * L * 16;
-                    if (fused)
-                        mttkrp_wave_kernel<FT, VEC, L, true, false, true><<<grid, 256, lds, st>>>(args);
-                    else
-                        mttkrp_wave_kernel<FT, VEC, L, false, false, true><<<grid, 256, lds, st>>>(args);
-                    return hipGetLastError();
-                }
-            }
             if (fused)
                 mttkrp_wave_kernel<FT, VEC, L, true, false, false><<<grid, 256, 0, st>>>(args);
             else if (args.perm)
@@ -839,11 +862,11 @@ hipError_t run_mttkrp(const MttkrpArgs &args, bool fused, bool wave, hipStream_t
         }
     }
     if (fused)
-        mttkrp_seg_kernel<FT, VEC, L, STRIDED, true, false><<<grid, 256, 0, st>>>(args);
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, true, false, false><<<grid, 256, 0, st>>>(args);
     else if (args.perm)
-        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, true><<<grid, 256, 0, st>>>(args);
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, true, false><<<grid, 256, 0, st>>>(args);
     else
-        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, false><<<grid, 256, 0, st>>>(args);
+        mttkrp_seg_kernel<FT, VEC, L, STRIDED, false, false, false><<<grid, 256, 0, st>>>(args);
     return hipGetLastError();
 }
 
