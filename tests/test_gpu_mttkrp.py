@@ -120,10 +120,11 @@ def test_orders_2_and_6_to_8(dims):
 @pytest.mark.parametrize("cfg,dims,R", [(3, (30_000, 3000, 208, 209), 64), (3, (30_000, 3000, 416, 417), 32),
                                          (2, (5000, 416, 417), 32), (5, (20_000, 2000, 1000, 208, 100), 64)])
 def test_lds_factor_at_its_size_limit(cfg, dims, R):
-    """The wave-run form (orders 3-5) reads the smallest factor after the second key from LDS
+    """Both kernel forms (orders 3-5) read the smallest factor after the second key from LDS
     when its rows fit 52 KiB: 208 rows of 256 bytes (fp32, R = 64) or 416 of 128 bytes (fp32
     R = 32, bf16 R = 64); one row more takes the global path. The factor that qualifies
-    differs by mode; fp32 and bf16 factors, every mode, against the oracle."""
+    differs by mode; fp32 and bf16 factors, every mode, and the fused CP gradient (whose
+    kernels stage the factor the same way), against the oracle."""
     sp = synth.CONFIGS[cfg].scaled(400_000, dims=dims)
     coo = synth.make_coo(sp)
     X = upload(coo)
@@ -135,6 +136,11 @@ def test_lds_factor_at_its_size_limit(cfg, dims, R):
     for n in range(coo.order):  # accumulation only: the fp32 bar against the bf16-rounded factors
         got = api().mttkrp(X, fd, n).cpu().numpy().astype(np.float64)
         assert rel(got, oracle.mttkrp(coo.dims, coo.inds, coo.vals, fo, n, "priv")) <= TOL_F32
+    loss, grads = api().cp_grad(X, factors_dev(f))
+    wl, wg = oracle.cp_grad(coo.dims, coo.inds, coo.vals, oracle_factors(f), "priv")
+    assert abs(loss.item() - wl) <= 1e-5 * wl
+    for n in range(coo.order):
+        assert rel(grads[n].cpu().numpy(), wg[n]) <= TOL_F32, n
 
 
 @pytest.mark.parametrize("R", [1, 3, 8, 24, 48, 100, 256])
